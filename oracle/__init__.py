@@ -1,0 +1,23 @@
+"""FP64 CPU oracle for the Cool-chic 5.0 encoding step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import it.  It shares no code with the
+GPU library and never imports it.
+
+Parity status by function (see the tests under tests/test_oracle_*.py):
+  philox4x32_10, box_muller      pinned (published known-answer vectors,
+                                 closed forms, moments)
+  softround, q_train, q_hard     pinned (closed forms, limits, continuity)
+  spatial_context, ifce_input    pinned (brute-force loops, causality)
+  arm_mlp                        pinned (special cases, explicit loops)
+  laplace_bin_prob, latent_bits  pinned (sum to one, closed forms)
+  upsample                       pinned (bicubic interpolation routine,
+                                 constants, explicit loops)
+  synthesis                      pinned (scipy correlation, explicit loops)
+  forward, loss_and_grad         pinned (closed-form totals, central finite
+                                 differences)
+  adam                           pinned (first- and second-step closed forms)
+  multi-step trajectories        parity unpinned beyond the per-step pins
+"""
+from .coolchic_ref import *  # noqa: F401,F403
+from .philox import philox4x32_10, box_muller, latent_noise  # noqa: F401

@@ -1,0 +1,199 @@
+"""Pins of the oracle's entropy model: causal context, IFCE, ARM, Laplace rate
+(Section III-A, eq. factorized-probability and eq. laplace-distribution)."""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+import torch
+import torch.nn.functional as Fnn
+
+import oracle
+from oracle import coolchic_ref as R
+from paper_2605_02726_amd import workloads as wl
+
+DT = torch.float64
+
+# The reading of the causal neighbourhood, written out by hand: the causal
+# half-plane ordered by distance, then row, then column.
+FIRST_24 = [(-1, 0), (0, -1), (-1, -1), (-1, 1), (-2, 0), (0, -2), (-2, -1), (-2, 1),
+            (-1, -2), (-1, 2), (-2, -2), (-2, 2), (-3, 0), (0, -3), (-3, -1), (-3, 1),
+            (-1, -3), (-1, 3), (-3, -2), (-3, 2), (-2, -3), (-2, 3), (-4, 0), (0, -4)]
+
+
+def test_offsets_match_hand_list_and_distance_shells():
+    assert R.causal_offsets(24) == FIRST_24
+    # Table II spatial-context sizes 6, 10 and 14 are whole distance shells
+    for s in (6, 10, 14):
+        d2 = [dy * dy + dx * dx for dy, dx in R.causal_offsets(s + 1)]
+        assert d2[s] > d2[s - 1]
+
+
+def _rand_grids(cfg, H, W, seed):
+    rng = np.random.default_rng(seed)
+    return [torch.tensor(rng.integers(-4, 5, size=(h, w)).astype(np.float64))
+            for h, w in R.grid_shapes(cfg, H, W)]
+
+
+def test_spatial_context_brute_force():
+    g = torch.tensor(np.random.default_rng(0).normal(size=(5, 7)))
+    c = R.spatial_context(g, FIRST_24)
+    for y in range(5):
+        for x in range(7):
+            for m, (dy, dx) in enumerate(FIRST_24):
+                yy, xx = y + dy, x + dx
+                v = float(g[yy, xx]) if (0 <= yy < 5 and 0 <= xx < 7) else 0.0
+                assert float(c[y * 7 + x, m]) == v
+
+
+def test_ifce_input_is_nearest_upsampling_of_coarser_grids():
+    cfg = wl.config_tiny().as_dict()
+    grids = _rand_grids(cfg, 16, 24, 1)
+    for k in range(cfg["L"] - 1):
+        r = R.ifce_input(grids, k)
+        h, w = grids[k].shape
+        for col, j in enumerate(range(k + 1, cfg["L"])):
+            up = Fnn.interpolate(grids[j][None, None], size=(h, w), mode="nearest")[0, 0]
+            assert torch.equal(r[:, col], up.reshape(-1))
+
+
+def _mlp_loops(cfg, P, c):
+    """Explicit per-position loops of the ARM (numpy)."""
+    n_layers = len(cfg["arm_hidden"]) + 1
+    out = []
+    for row in c.numpy():
+        h = row
+        for i in range(n_layers):
+            Wt = P[f"arm.{i}.w"].numpy()
+            b = P[f"arm.{i}.b"].numpy()
+            h = np.array([sum(Wt[o, q] * h[q] for q in range(len(h))) + b[o]
+                          for o in range(Wt.shape[0])])
+            if i < n_layers - 1:
+                h = np.maximum(h, 0.0)
+        if cfg["arm_stab"]:
+            Ws, bs = P["arm.stab.w"].numpy(), P["arm.stab.b"].numpy()
+            h = h + np.array([sum(Ws[o, q] * row[q] for q in range(len(row))) + bs[o]
+                              for o in range(2)])
+        out.append(h)
+    return np.array(out)
+
+
+def test_arm_mlp_matches_explicit_loops():
+    cfg = wl.config_tiny().as_dict()
+    theta = torch.tensor(wl.init_params(wl.config_tiny(), 3, arm_out_zero=False), dtype=DT)
+    P = R.unpack_params(cfg, theta)
+    c = torch.tensor(np.random.default_rng(2).normal(size=(9, 8)))
+    mu, ls = R.arm_mlp(cfg, P, c)
+    ref = _mlp_loops(cfg, P, c)
+    assert np.allclose(mu.numpy(), ref[:, 0], atol=1e-12)
+    assert np.allclose(ls.numpy(), ref[:, 1], atol=1e-12)
+
+
+def test_arm_zero_weights_output_is_last_bias():
+    cfg = wl.config_hop().as_dict()
+    theta = torch.zeros(R.n_params(cfg), dtype=DT)
+    P = R.unpack_params(cfg, theta)
+    P["arm.2.b"][:] = torch.tensor([0.25, -1.5], dtype=DT)
+    c = torch.tensor(np.random.default_rng(0).normal(size=(11, 30)))
+    mu, ls = R.arm_mlp(cfg, P, c)
+    assert torch.all(mu == 0.25) and torch.all(ls == -1.5)
+    # stabilizer alone is an affine map of the context
+    P["arm.stab.w"][:] = torch.tensor(np.random.default_rng(1).normal(size=(2, 30)))
+    mu, ls = R.arm_mlp(cfg, P, c)
+    ref = c.numpy() @ P["arm.stab.w"].numpy().T + np.array([0.25, -1.5])
+    assert np.allclose(mu.numpy(), ref[:, 0]) and np.allclose(ls.numpy(), ref[:, 1])
+
+
+def test_ifce_zero_weights_reduce_to_spatial_arm():
+    cfg = wl.config_hop().as_dict()
+    theta = torch.tensor(wl.init_params(wl.config_hop(), 4, arm_out_zero=False), dtype=DT)
+    P = R.unpack_params(cfg, theta)
+    for k in range(3):
+        P[f"ifce.{k}.w"].zero_()
+        P[f"ifce.{k}.b"].zero_()
+    grids = _rand_grids(cfg, 64, 64, 5)
+    c = R.arm_context(cfg, P, grids, 0)
+    assert torch.all(c[:, 24:] == 0)
+    assert torch.equal(c[:, :24], R.spatial_context(grids[0], FIRST_24))
+
+
+CFG_LAP = dict(logscale_min=-4.6, logscale_max=5.0, p_min=0.0)
+
+
+@pytest.mark.parametrize("mu,ls", [(0.0, 0.0), (0.3, -2.0), (-1.7, 1.3), (2.49, 4.9), (0.5, -4.5)])
+def test_laplace_bins_sum_to_one(mu, ls):
+    b = math.exp(ls)
+    K = int(60 * b) + 60
+    n = torch.arange(-K, K + 1, dtype=DT)
+    p = R.laplace_bin_prob(n, torch.full_like(n, mu), torch.full_like(n, ls), CFG_LAP)
+    # mass outside [-K-1/2, K+1/2] in closed form
+    tails = 0.5 * math.exp(-(K + 0.5 - mu) / b) + 0.5 * math.exp(-(K + 0.5 + mu) / b)
+    assert float(p.sum()) + tails == pytest.approx(1.0, abs=1e-12)
+    assert torch.all(p >= 0)
+
+
+def test_laplace_matches_scipy():
+    rng = np.random.default_rng(3)
+    yh = rng.normal(scale=3, size=500)
+    mu = rng.normal(scale=2, size=500)
+    ls = rng.uniform(-4, 4.5, size=500)
+    p = R.laplace_bin_prob(torch.tensor(yh), torch.tensor(mu), torch.tensor(ls), CFG_LAP).numpy()
+    b = np.exp(ls)
+    ref = scipy.stats.laplace.cdf(yh + 0.5, mu, b) - scipy.stats.laplace.cdf(yh - 0.5, mu, b)
+    big = ref > 1e-12
+    assert np.allclose(p[big], ref[big], rtol=1e-9)
+
+
+def test_rate_closed_form_single_latent():
+    # mu = 0, b = 1, yhat = 0: p = 1 - e^(-1/2), bits = -log2(1 - e^(-1/2))
+    bits = R.latent_bits(torch.zeros(1, dtype=DT), torch.zeros(1, dtype=DT),
+                         torch.zeros(1, dtype=DT), dict(CFG_LAP, p_min=2 ** -16))
+    assert float(bits) == pytest.approx(1.3456768717, abs=1e-10)
+    # floor: a far-away symbol costs exactly 16 bits
+    bits = R.latent_bits(torch.tensor([40.0], dtype=DT), torch.zeros(1, dtype=DT),
+                         torch.zeros(1, dtype=DT), dict(CFG_LAP, p_min=2 ** -16))
+    assert float(bits) == 16.0
+
+
+@pytest.mark.parametrize("which,H,W,expect", [("small", 64, 64, 7348.741), ("hop", 512, 768, 705479.17)])
+def test_all_zero_latents_total_rate(which, H, W, expect):
+    mc = wl.config_small() if which == "small" else wl.config_hop()
+    cfg = mc.as_dict()
+    P = R.unpack_params(cfg, torch.tensor(wl.init_params(mc, 0), dtype=DT))
+    grids = [torch.zeros(h, w, dtype=DT) for h, w in R.grid_shapes(cfg, H, W)]
+    total, _, _ = R.rate_bits(cfg, P, grids)
+    assert float(total) == pytest.approx(expect, abs=0.01)
+    assert float(total) / (H * W) == pytest.approx(1.794126, abs=1e-6)
+
+
+def test_causality_brute_force():
+    """An ARM output never depends on a later position of its grid or on a
+    finer grid (decoding order of Section III-A.2)."""
+    mc = wl.config_tiny()
+    cfg = mc.as_dict()
+    H = W = 8
+    P = R.unpack_params(cfg, torch.tensor(wl.init_params(mc, 9, arm_out_zero=False, scale=3.0),
+                                          dtype=DT))
+    base = _rand_grids(cfg, H, W, 11)
+
+    def outputs(grids):
+        return [torch.stack(R.arm_mlp(cfg, P, R.arm_context(cfg, P, grids, k)), 1)
+                for k in range(cfg["L"])]
+
+    ref = outputs(base)
+    for k in range(cfg["L"]):
+        h, w = base[k].shape
+        for j in range(h * w):
+            g = [x.clone() for x in base]
+            g[k].view(-1)[j] += 3.0
+            out = outputs(g)
+            # same grid: positions up to and including j unchanged
+            assert torch.equal(out[k][:j + 1], ref[k][:j + 1])
+            # coarser grids (decoded before grid k) unchanged
+            for kk in range(k + 1, cfg["L"]):
+                assert torch.equal(out[kk], ref[kk])
+            # and the perturbation is visible somewhere later, or on a finer grid
+            changed = any(not torch.equal(out[kk], ref[kk]) for kk in range(k)) or \
+                not torch.equal(out[k][j + 1:], ref[k][j + 1:])
+            if j < h * w - 1 or k > 0:
+                assert changed
