@@ -1,0 +1,156 @@
+/*
+ * coolchic.h -- C ABI of the MI355X (gfx950) Cool-chic 5.0 encoding step.
+ *
+ * One encoding iteration (Section IV of the paper) for one image or a batch
+ * of images: the training quantisation proxy of the latent grids (Section
+ * IV-C, eq. q-train / eq. softround), the autoregressive Laplace entropy model
+ * with inter-feature context that gives the rate (Section III-A, eq.
+ * factorized-probability / eq. laplace-distribution), the learned upsampling
+ * and the synthesis (Section III-B) with linear stabilizers (Section III-C),
+ * the MSE + lambda * rate cost (Section IV-A, eq. training-loss), its gradient
+ * and an Adam update (Section IV-B).
+ *
+ * Conventions shared by every call
+ *   - Every function returns CC_OK (0) or a negative error code; the message
+ *     of the last failure on the calling thread is cc_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - Device pointers are HIP device addresses on the current device; the
+ *     caller owns every device buffer (the state slab, images, outputs).  The
+ *     library owns only the opaque cc_state descriptor (host memory).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work asynchronously on it; a call that fills a host output pointer
+ *     synchronises the stream before returning.
+ *   - The library never allocates device memory: all scratch lives in the
+ *     caller-provided state slab of cc_state_bytes() bytes.
+ *   - Latent layout ("flat pyramid"): grid k = 0 .. L-1 of shape
+ *     (H/2^k, W/2^k) stored row-major, grid 0 first.
+ *   - Decoder parameter layout: ARM layers (W [out,in] row-major, then b),
+ *     ARM stabilizer (W [2,ctx], b [2]), IFCE k = 0..n_ifce_grids-1
+ *     (W [F, L-k-1], b [F]), upsampling level j = 1..L-1 (4 free taps h0..h3
+ *     of the symmetric kernel h0 h1 h2 h3 h3 h2 h1 h0), synthesis 1x1 layers
+ *     (W [out,in], b), synthesis stabilizer (W [3,L], b [3]), residual 3x3
+ *     layers (W [3,3,3,3] as out,in,ky,kx, b [3]).
+ *   - Images are planar float32 [3, H, W] with values in [0, 1].
+ */
+#ifndef COOLCHIC_H
+#define COOLCHIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CC_OK = 0,
+  CC_EINVAL = -1,      /* bad argument, unsupported shape or configuration */
+  CC_ENOMEM = -2,      /* state slab smaller than cc_state_bytes()          */
+  CC_EDEVICE = -3,     /* a HIP runtime call failed                         */
+  CC_ENONFINITE = -4,  /* the loss of an earlier step was NaN or infinite   */
+  CC_ESTATE = -5       /* state not initialised or inconsistent             */
+};
+
+enum { CC_SOFT = 0, CC_HARD = 1 };              /* quantisation mode   */
+enum { CC_FP32_PLAIN = 0, CC_BF16_FUSED = 1 };  /* arithmetic of the MLPs */
+
+#define CC_MAX_BATCH 32
+
+/* Decoder shape (Table II gives the named presets).  The ARM always has
+ * two hidden layers (Table II).  Supported shapes are listed by
+ * cc_config_supported(). */
+typedef struct cc_config {
+  int L;              /* latent grids, 2..8                                  */
+  int n_spatial;      /* causal spatial neighbours s                         */
+  int n_ifce_feat;    /* inter-feature context size F (0 = no IFCE)          */
+  int n_ifce_grids;   /* grids 0..n_ifce_grids-1 use an IFCE, 0..3           */
+  int arm_hidden[2];  /* widths of the two hidden ARM layers                 */
+  int arm_stab;       /* 1 = linear stabilizer beside the ARM                */
+  int n_syn_hidden;   /* hidden 1x1 synthesis layers, 1 or 2                 */
+  int syn_hidden[2];
+  int syn_stab;       /* 1 = linear stabilizer beside the synthesis trunk    */
+  int n_res;          /* residual 3x3 post-filter layers, 0..4               */
+  float logscale_min; /* clamp of the ARM log-scale output                   */
+  float logscale_max;
+  float p_min;        /* floor of a latent's probability                     */
+  int precision;      /* CC_FP32_PLAIN or CC_BF16_FUSED                      */
+} cc_config;
+
+/* Per-iteration scalars (Table I schedules are evaluated by the caller). */
+typedef struct cc_step_params {
+  int64_t t;          /* 1-based iteration: noise counter and Adam step      */
+  float lr;           /* Adam learning rate                                  */
+  float temperature;  /* softround temperature T                             */
+  float sigma;        /* std of the Gaussian noise                           */
+  int quant_mode;     /* CC_SOFT: s_T(s_T(y) + n); CC_HARD: round half even  */
+  int update_latents; /* 0 = latents frozen (hard-round stage)               */
+} cc_step_params;
+
+typedef struct cc_rd_result {
+  double bits, bpp, mse, psnr, loss;
+} cc_rd_result;
+
+typedef struct cc_state cc_state;
+
+/* 1 if the GPU path supports this decoder shape and image size, else 0.
+ * H and W must be multiples of 2^(L-1). */
+int cc_config_supported(const cc_config* cfg, int H, int W);
+
+/* Sizes. */
+int64_t cc_n_latents(const cc_config* cfg, int H, int W);
+int cc_n_params(const cc_config* cfg);
+size_t cc_state_bytes(const cc_config* cfg, int H, int W);
+
+/* Initialise a state in the caller's device slab `mem` (>= cc_state_bytes,
+ * 256-byte aligned).  Copies the image in, sets the latents (host array of
+ * cc_n_latents floats, NULL = all zero) and decoder parameters (host array of
+ * cc_n_params floats, NULL = seeded default: U(+-1/sqrt(fan_in)) weights and
+ * biases, zero ARM output layer, bicubic upsampling), zero Adam moments.
+ * `seed` keys the Philox noise.  Synchronises `stream`. */
+int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev,
+                  double lambda, uint64_t seed, const float* init_latents_host,
+                  const float* init_params_host, void* mem, size_t bytes,
+                  void* stream, cc_state** out);
+
+/* One encoding iteration (forward, backward, Adam).  If `out3` is not NULL
+ * it receives (loss, bits, mse) of this iteration's forward pass and the
+ * stream is synchronised; a non-finite loss then returns CC_ENONFINITE and
+ * marks the state.  With `out3` NULL the call is fully asynchronous. */
+int cc_encode_step(cc_state* s, const cc_step_params* p, double* out3, void* stream);
+
+/* The same iteration for n <= CC_MAX_BATCH independent states in one set of
+ * launches; p[i] applies to states[i]; out (3 n doubles, may be NULL). */
+int cc_encode_step_batch(cc_state* const* states, int n, const cc_step_params* p,
+                         double* out, void* stream);
+
+/* Loss of the current state for the iteration's quantisation (noise from
+ * p->t), without gradient or update: (loss, bits, mse).  Synchronises. */
+int cc_eval_loss(cc_state* s, const cc_step_params* p, double* out3, void* stream);
+
+/* Rate and distortion with hard quantisation, no gradient.  Synchronises. */
+int cc_rd_eval(cc_state* s, cc_rd_result* out, void* stream);
+
+/* Decoded image [3, H, W] (hard quantisation -> upsampling -> synthesis)
+ * into the caller's device buffer. */
+int cc_decode(cc_state* s, float* out_img_dev, void* stream);
+
+/* Copy state to / from host arrays (any pointer may be NULL to skip).
+ * latents: cc_n_latents floats; params, grad: cc_n_params floats for the
+ * decoder part, latents first for `grad_host` (n_latents + n_params). */
+int cc_get_state(cc_state* s, float* latents, float* params, float* adam_m,
+                 float* adam_v, int64_t* t, void* stream);
+int cc_set_state(cc_state* s, const float* latents, const float* params,
+                 const float* adam_m, const float* adam_v, int64_t t, void* stream);
+/* Gradient of the last cc_encode_step (n_latents + n_params floats). */
+int cc_get_grad(cc_state* s, float* grad_host, void* stream);
+
+/* Switch the arithmetic of the MLP kernels (CC_FP32_PLAIN / CC_BF16_FUSED). */
+int cc_set_precision(cc_state* s, int precision);
+
+void cc_free_state(cc_state* s);
+const char* cc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COOLCHIC_H */

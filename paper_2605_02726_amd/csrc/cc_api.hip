@@ -1,0 +1,764 @@
+// Host side of the Cool-chic encode-step library: configuration checks,
+// state-slab layout, launch planning over a batch of images and the C ABI
+// declared in include/coolchic.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "cc_internal.h"
+
+int cc_arm_shape_supported(int S, int F, int H1, int H2);
+int cc_syn_shape_supported(int nh, int w1, int w2);
+int cc_launch_arm_plain(const Launch& l, const DevDesc& h, int bwd, hipStream_t st);
+int cc_launch_arm_fused(const Launch& l, const DevDesc& h, int bwd, hipStream_t st);
+int cc_arm_fused_supported(const DevDesc& h);
+int cc_launch_syn_fwd_plain(const Launch& l, const DevDesc& h, int final_mse, hipStream_t st);
+int cc_launch_syn_bwd_plain(const Launch& l, const DevDesc& h, int src_b, hipStream_t st);
+int cc_launch_res_bwd2(const Launch& l, int r, int src_b, hipStream_t st);
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) return fail(CC_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Causal neighbours in decoding order: the half-plane {dy < 0, or dy = 0 and
+// dx < 0} sorted by (dy^2 + dx^2, dy, dx).
+void causal_offsets(int s, int* dy, int* dx) {
+  struct O { int y, x; };
+  std::vector<O> c;
+  for (int y = -8; y <= 0; ++y)
+    for (int x = -8; x <= 8; ++x)
+      if (y < 0 || x < 0) c.push_back({y, x});
+  std::stable_sort(c.begin(), c.end(), [](const O& a, const O& b) {
+    const int da = a.y * a.y + a.x * a.x, db = b.y * b.y + b.x * b.x;
+    if (da != db) return da < db;
+    if (a.y != b.y) return a.y < b.y;
+    return a.x < b.x;
+  });
+  for (int m = 0; m < s; ++m) {
+    dy[m] = c[m].y;
+    dx[m] = c[m].x;
+  }
+}
+
+struct Layout {
+  DevDesc h{};          // host copy (pointers filled relative to a base)
+  size_t bytes = 0;
+  size_t off_desc = 0, off_img, off_theta, off_m, off_v, off_grad, off_yhat, off_dq, off_dyd,
+         off_dyq, off_dc, off_df, off_U, off_dU, off_X, off_dXa, off_dXb, off_wp, off_wp2,
+         off_agt, off_sgt, off_lpb, off_lpm, off_scal;
+  std::vector<unsigned> arm_gtab, syn_gtab;
+  int syn_o[7];
+};
+
+int check_config(const cc_config* c, int H, int W) {
+  if (!c) return fail(CC_EINVAL, "config is NULL");
+  if (c->L < 2 || c->L > CC_MAX_L) return fail(CC_EINVAL, "L=%d outside [2, %d]", c->L, CC_MAX_L);
+  const int m = 1 << (c->L - 1);
+  if (H <= 0 || W <= 0 || H % m || W % m)
+    return fail(CC_EINVAL, "image %dx%d: sides must be positive multiples of 2^(L-1)=%d", H, W, m);
+  if ((long long)H * W > (1ll << 26)) return fail(CC_EINVAL, "image %dx%d too large", H, W);
+  if (c->n_spatial < 1 || c->n_spatial > CC_MAX_S) return fail(CC_EINVAL, "n_spatial=%d", c->n_spatial);
+  if (c->n_ifce_feat < 0 || c->n_ifce_grids < 0 || c->n_ifce_grids > 3 ||
+      c->n_ifce_grids > c->L - 1 || (c->n_ifce_feat == 0) != (c->n_ifce_grids == 0))
+    return fail(CC_EINVAL, "IFCE F=%d grids=%d", c->n_ifce_feat, c->n_ifce_grids);
+  if (!cc_arm_shape_supported(c->n_spatial, c->n_ifce_feat, c->arm_hidden[0], c->arm_hidden[1]))
+    return fail(CC_EINVAL, "ARM shape s=%d F=%d hidden=%d,%d not compiled in", c->n_spatial,
+                c->n_ifce_feat, c->arm_hidden[0], c->arm_hidden[1]);
+  if (c->n_syn_hidden < 1 || c->n_syn_hidden > 2 ||
+      !cc_syn_shape_supported(c->n_syn_hidden, c->syn_hidden[0], c->syn_hidden[1]))
+    return fail(CC_EINVAL, "synthesis shape not compiled in");
+  if (c->n_res < 0 || c->n_res > 4) return fail(CC_EINVAL, "n_res=%d outside [0, 4]", c->n_res);
+  if (!(c->logscale_min < c->logscale_max)) return fail(CC_EINVAL, "log-scale clamp");
+  if (!(c->p_min > 0.0f && c->p_min < 1.0f)) return fail(CC_EINVAL, "p_min must be in (0, 1)");
+  if (c->precision != CC_FP32_PLAIN && c->precision != CC_BF16_FUSED)
+    return fail(CC_EINVAL, "precision=%d", c->precision);
+  return CC_OK;
+}
+
+void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
+  DevDesc& h = Lo.h;
+  memset(&h, 0, sizeof h);
+  h.H = H;
+  h.W = W;
+  h.L = c->L;
+  h.S = c->n_spatial;
+  h.F = c->n_ifce_feat;
+  h.G = c->n_ifce_grids;
+  h.H1 = c->arm_hidden[0];
+  h.H2 = c->arm_hidden[1];
+  h.ctx = h.S + h.F;
+  h.arm_stab = c->arm_stab ? 1 : 0;
+  h.syn_stab = c->syn_stab ? 1 : 0;
+  h.n_syn_hidden = c->n_syn_hidden;
+  h.n_res = c->n_res;
+  h.syn_w[0] = c->L;
+  for (int i = 0; i < c->n_syn_hidden; ++i) h.syn_w[1 + i] = c->syn_hidden[i];
+  h.syn_w[1 + c->n_syn_hidden] = 3;
+  int off = 0;
+  for (int k = 0; k < c->L; ++k) {
+    h.gh[k] = H >> k;
+    h.gw[k] = W >> k;
+    h.goff[k] = off;
+    off += h.gh[k] * h.gw[k];
+  }
+  h.n_lat = off;
+  causal_offsets(h.S, h.dy, h.dx);
+
+  // decoder parameter offsets in the documented order
+  int p = 0;
+  const int aw[4] = {h.ctx, h.H1, h.H2, 2};
+  for (int i = 0; i < 3; ++i) {
+    h.p_aw[i] = p;
+    p += aw[i + 1] * aw[i];
+    h.p_ab[i] = p;
+    p += aw[i + 1];
+  }
+  h.p_asw = h.p_asb = -1;
+  if (h.arm_stab) {
+    h.p_asw = p;
+    p += 2 * h.ctx;
+    h.p_asb = p;
+    p += 2;
+  }
+  for (int k = 0; k < h.G; ++k) {
+    h.p_iw[k] = p;
+    p += h.F * (h.L - k - 1);
+    h.p_ib[k] = p;
+    p += h.F;
+  }
+  h.n_arm_par = p;
+  for (int j = 1; j < h.L; ++j) {
+    h.p_ups[j] = p;
+    p += 4;
+  }
+  const int nsl = h.n_syn_hidden + 1;
+  for (int i = 0; i < nsl; ++i) {
+    h.p_sw[i] = p;
+    p += h.syn_w[i + 1] * h.syn_w[i];
+    h.p_sb[i] = p;
+    p += h.syn_w[i + 1];
+  }
+  h.p_ssw = h.p_ssb = -1;
+  if (h.syn_stab) {
+    h.p_ssw = p;
+    p += 3 * h.L;
+    h.p_ssb = p;
+    p += 3;
+  }
+  const int syn_end = p;
+  for (int r = 0; r < h.n_res; ++r) {
+    h.p_rw[r] = p;
+    p += 81;
+    h.p_rb[r] = p;
+    p += 3;
+  }
+  h.n_par = p;
+  h.n_theta = h.n_lat + h.n_par;
+
+  h.lmin = c->logscale_min;
+  h.lmax = c->logscale_max;
+  h.pmin = c->p_min;
+  h.bits_max = (float)(-log2((double)c->p_min));
+
+  // producer geometry
+  for (int k = 0; k < h.L; ++k) h.arm_nchunk += cdiv(h.gh[k] * h.gw[k], CC_ARM_CHUNK);
+  h.arm_nwg = cdiv(h.arm_nchunk, CC_ARM_CPW);
+  const int npix = H * W;
+  h.syn_nchunk = cdiv(npix, CC_SYN_CHUNK);
+  h.syn_nwg = cdiv(h.syn_nchunk, CC_SYN_CPW);
+  h.pix_ntile = cdiv(npix, CC_PIX_TILE);
+  h.pix_nwg = h.pix_ntile;
+  h.lat_ntile = cdiv(h.n_lat, CC_ELT_TILE);
+  long long wpo = 0;
+  int q = 0;
+  h.prod_arm = q;
+  h.prod[q++] = {0, h.n_arm_par, h.arm_nwg, 0, wpo};
+  wpo += (long long)h.arm_nwg * h.n_arm_par;
+  h.prod_ups1 = q;
+  for (int j = 1; j < h.L; ++j) {
+    const int rows = cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE);
+    h.prod[q++] = {h.p_ups[j], 4, rows, 0, wpo};
+    wpo += (long long)rows * 4;
+  }
+  h.prod_syn = q;
+  h.prod[q++] = {h.p_sw[0], syn_end - h.p_sw[0], h.syn_nwg, 0, wpo};
+  wpo += (long long)h.syn_nwg * (syn_end - h.p_sw[0]);
+  h.prod_res0 = q;
+  for (int r = 0; r < h.n_res; ++r) {
+    h.prod[q++] = {h.p_rw[r], 84, h.pix_ntile, 0, wpo};
+    wpo += (long long)h.pix_ntile * 84;
+  }
+  h.nprod = q;
+
+  // weight-gradient tables: (index into gradient vector, index into
+  // activation vector, grid requirement) per parameter, matching the LDS row
+  // layouts of the ARM and synthesis backward kernels.
+  {
+    const int CTX = h.ctx, RM = CC_MAX_L - 1;
+    const int O_H1 = CTX, O_H2 = O_H1 + h.H1, O_R = O_H2 + h.H2, O_DH1 = O_R + RM,
+              O_DH2 = O_DH1 + h.H1, O_DO = O_DH2 + h.H2, O_DF = O_DO + 2, O_ONE = O_DF + h.F;
+    auto ent = [](int a, int b, int k) {
+      return (unsigned)a | ((unsigned)b << 8) | ((unsigned)(k & 0xFF) << 16);
+    };
+    std::vector<unsigned>& t = Lo.arm_gtab;
+    t.assign(h.n_arm_par, 0xFFFFFFFFu);
+    for (int a = 0; a < h.H1; ++a)
+      for (int b = 0; b < CTX; ++b) t[h.p_aw[0] + a * CTX + b] = ent(O_DH1 + a, b, 0xFF);
+    for (int a = 0; a < h.H1; ++a) t[h.p_ab[0] + a] = ent(O_DH1 + a, O_ONE, 0xFF);
+    for (int a = 0; a < h.H2; ++a)
+      for (int b = 0; b < h.H1; ++b) t[h.p_aw[1] + a * h.H1 + b] = ent(O_DH2 + a, O_H1 + b, 0xFF);
+    for (int a = 0; a < h.H2; ++a) t[h.p_ab[1] + a] = ent(O_DH2 + a, O_ONE, 0xFF);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < h.H2; ++b) t[h.p_aw[2] + a * h.H2 + b] = ent(O_DO + a, O_H2 + b, 0xFF);
+    for (int a = 0; a < 2; ++a) t[h.p_ab[2] + a] = ent(O_DO + a, O_ONE, 0xFF);
+    if (h.arm_stab) {
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < CTX; ++b) t[h.p_asw + a * CTX + b] = ent(O_DO + a, b, 0xFF);
+      for (int a = 0; a < 2; ++a) t[h.p_asb + a] = ent(O_DO + a, O_ONE, 0xFF);
+    }
+    for (int k = 0; k < h.G; ++k) {
+      const int nin = h.L - k - 1;
+      for (int f = 0; f < h.F; ++f)
+        for (int qq = 0; qq < nin; ++qq) t[h.p_iw[k] + f * nin + qq] = ent(O_DF + f, O_R + qq, k);
+      for (int f = 0; f < h.F; ++f) t[h.p_ib[k] + f] = ent(O_DF + f, O_ONE, k);
+    }
+  }
+  {
+    const int W1 = h.syn_w[1], NH = h.n_syn_hidden, HW2 = NH == 2 ? h.syn_w[2] : 0;
+    const int WL = NH == 2 ? h.syn_w[2] : W1;
+    const int O_Z = 0, O_H1 = CC_MAX_L, O_H2 = O_H1 + W1, O_DH1 = O_H2 + HW2,
+              O_DH2 = O_DH1 + W1, O_DO = O_DH2 + HW2, O_ONE = O_DO + 3;
+    auto ent = [](int a, int b) { return (unsigned)a | ((unsigned)b << 8) | (0xFFu << 16); };
+    const int base = h.p_sw[0];
+    std::vector<unsigned>& t = Lo.syn_gtab;
+    t.assign(syn_end - base, 0xFFFFFFFFu);
+    for (int a = 0; a < W1; ++a)
+      for (int b = 0; b < h.L; ++b) t[h.p_sw[0] - base + a * h.L + b] = ent(O_DH1 + a, O_Z + b);
+    for (int a = 0; a < W1; ++a) t[h.p_sb[0] - base + a] = ent(O_DH1 + a, O_ONE);
+    if (NH == 2) {
+      for (int a = 0; a < HW2; ++a)
+        for (int b = 0; b < W1; ++b) t[h.p_sw[1] - base + a * W1 + b] = ent(O_DH2 + a, O_H1 + b);
+      for (int a = 0; a < HW2; ++a) t[h.p_sb[1] - base + a] = ent(O_DH2 + a, O_ONE);
+    }
+    const int O_HL = NH == 2 ? O_H2 : O_H1;
+    for (int c3 = 0; c3 < 3; ++c3)
+      for (int b = 0; b < WL; ++b) t[h.p_sw[NH] - base + c3 * WL + b] = ent(O_DO + c3, O_HL + b);
+    for (int c3 = 0; c3 < 3; ++c3) t[h.p_sb[NH] - base + c3] = ent(O_DO + c3, O_ONE);
+    if (h.syn_stab) {
+      for (int c3 = 0; c3 < 3; ++c3)
+        for (int b = 0; b < h.L; ++b) t[h.p_ssw - base + c3 * h.L + b] = ent(O_DO + c3, O_Z + b);
+      for (int c3 = 0; c3 < 3; ++c3) t[h.p_ssb - base + c3] = ent(O_DO + c3, O_ONE);
+    }
+  }
+
+  // slab layout
+  size_t o = 0;
+  auto take = [&](size_t n) {
+    const size_t r = o;
+    o = al256(o + n);
+    return r;
+  };
+  Lo.off_desc = take(sizeof(DevDesc));
+  Lo.off_img = take(sizeof(float) * 3 * (size_t)npix);
+  Lo.off_theta = take(sizeof(float) * (size_t)h.n_theta);
+  Lo.off_m = take(sizeof(float) * (size_t)h.n_theta);
+  Lo.off_v = take(sizeof(float) * (size_t)h.n_theta);
+  Lo.off_grad = take(sizeof(float) * (size_t)h.n_theta);
+  Lo.off_yhat = take(sizeof(float) * (size_t)h.n_lat);
+  Lo.off_dq = take(sizeof(float) * (size_t)h.n_lat);
+  Lo.off_dyd = take(sizeof(float) * (size_t)h.n_lat);
+  Lo.off_dyq = take(sizeof(float) * (size_t)h.n_lat);
+  Lo.off_dc = take(sizeof(float) * (size_t)h.S * h.n_lat);
+  size_t dfn = 0;
+  for (int cg = 0; cg < h.G; ++cg)
+    for (int f = 0; cg + f < h.L; ++f) {
+      h.dfoff[cg][f] = (int)dfn;
+      dfn += (size_t)h.F * h.gh[cg + f] * h.gw[cg + f];
+    }
+  Lo.off_df = take(sizeof(float) * std::max<size_t>(dfn, 1));
+  size_t un = 0;
+  for (int j = 1; j < h.L; ++j) {
+    h.uoff[j] = (int)un;
+    un += (size_t)(h.L - j) * h.gh[j - 1] * h.gw[j - 1];
+  }
+  Lo.off_U = take(sizeof(float) * un);
+  Lo.off_dU = take(sizeof(float) * un);
+  Lo.off_X = take(sizeof(float) * (size_t)(h.n_res + 1) * 3 * npix);
+  Lo.off_dXa = take(sizeof(float) * 3 * (size_t)npix);
+  Lo.off_dXb = take(sizeof(float) * 3 * (size_t)npix);
+  Lo.off_wp = take(sizeof(float) * (size_t)wpo);
+  Lo.off_wp2 = take(sizeof(double) * (size_t)CC_WRED_SPLIT * h.n_par);
+  Lo.off_agt = take(sizeof(unsigned) * (size_t)h.n_arm_par);
+  Lo.off_sgt = take(sizeof(unsigned) * Lo.syn_gtab.size());
+  Lo.off_lpb = take(sizeof(double) * (size_t)h.arm_nwg);
+  Lo.off_lpm = take(sizeof(double) * (size_t)h.pix_ntile);
+  Lo.off_scal = take(sizeof(double) * 4);
+  Lo.bytes = o;
+}
+
+void set_pointers(Layout& Lo, char* base) {
+  DevDesc& h = Lo.h;
+  h.img = (float*)(base + Lo.off_img);
+  h.theta = (float*)(base + Lo.off_theta);
+  h.m = (float*)(base + Lo.off_m);
+  h.v = (float*)(base + Lo.off_v);
+  h.grad = (float*)(base + Lo.off_grad);
+  h.yhat = (float*)(base + Lo.off_yhat);
+  h.dq = (float*)(base + Lo.off_dq);
+  h.dyd = (float*)(base + Lo.off_dyd);
+  h.dyq = (float*)(base + Lo.off_dyq);
+  h.dc = (float*)(base + Lo.off_dc);
+  h.df = (float*)(base + Lo.off_df);
+  h.U = (float*)(base + Lo.off_U);
+  h.dU = (float*)(base + Lo.off_dU);
+  h.X = (float*)(base + Lo.off_X);
+  h.dXa = (float*)(base + Lo.off_dXa);
+  h.dXb = (float*)(base + Lo.off_dXb);
+  h.wp = (float*)(base + Lo.off_wp);
+  h.wp2 = (double*)(base + Lo.off_wp2);
+  h.arm_gtab = (unsigned*)(base + Lo.off_agt);
+  h.syn_gtab = (unsigned*)(base + Lo.off_sgt);
+  h.lp_bits = (double*)(base + Lo.off_lpb);
+  h.lp_mse = (double*)(base + Lo.off_lpm);
+  h.scal = (double*)(base + Lo.off_scal);
+}
+
+// Seeded default decoder parameters (splitmix64 uniforms).
+struct SplitMix {
+  uint64_t s;
+  double next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  }
+};
+
+void default_params(const DevDesc& h, uint64_t seed, std::vector<float>& P) {
+  P.assign(h.n_par, 0.0f);
+  SplitMix g{seed ^ 0x5EEDC0DEull};
+  auto fill = [&](int off, int n, int fan_in) {
+    const double b = 1.0 / sqrt((double)fan_in);
+    for (int i = 0; i < n; ++i) P[off + i] = (float)((2.0 * g.next() - 1.0) * b);
+  };
+  fill(h.p_aw[0], h.H1 * h.ctx + h.H1, h.ctx);
+  fill(h.p_aw[1], h.H2 * h.H1 + h.H2, h.H1);
+  for (int k = 0; k < h.G; ++k) fill(h.p_iw[k], h.F * (h.L - k - 1) + h.F, h.L - k - 1);
+  const float bic[4] = {-0.03515625f, -0.10546875f, 0.26171875f, 0.87890625f};
+  for (int j = 1; j < h.L; ++j)
+    for (int t = 0; t < 4; ++t) P[h.p_ups[j] + t] = bic[t];
+  for (int i = 0; i <= h.n_syn_hidden; ++i)
+    fill(h.p_sw[i], h.syn_w[i + 1] * h.syn_w[i] + h.syn_w[i + 1], h.syn_w[i]);
+  if (h.syn_stab) fill(h.p_ssw, 3 * h.L + 3, h.L);
+  for (int r = 0; r < h.n_res; ++r) fill(h.p_rw[r], 84, 27);
+}
+
+}  // namespace
+
+struct cc_state {
+  cc_config cfg;
+  Layout lo;
+  DevDesc* ddev;   // device copy
+  char* base;
+  int precision;
+  int nonfinite;
+  int64_t t;
+  int device;
+};
+
+namespace {
+
+// ------------------------------------------------------- launch planning --
+template <class F>
+Launch plan(cc_state* const* s, int n, F count) {
+  Launch l;
+  memset(&l, 0, sizeof l);
+  l.n = n;
+  int acc = 0;
+  for (int i = 0; i < n; ++i) {
+    l.tile0[i] = acc;
+    l.d[i] = s[i]->ddev;
+    acc += count(s[i]->lo.h);
+  }
+  l.tile0[n] = acc;
+  return l;
+}
+
+bool same_shape(const cc_state* a, const cc_state* b) {
+  const DevDesc &x = a->lo.h, &y = b->lo.h;
+  return x.L == y.L && x.S == y.S && x.F == y.F && x.G == y.G && x.H1 == y.H1 && x.H2 == y.H2 &&
+         x.n_syn_hidden == y.n_syn_hidden && x.syn_w[1] == y.syn_w[1] &&
+         x.syn_w[2] == y.syn_w[2] && x.n_res == y.n_res && a->precision == b->precision;
+}
+
+StepArgs step_args(const cc_step_params& p) {
+  StepArgs a{};
+  const double T = p.temperature > 0.0f ? (double)p.temperature : 1.0;
+  a.T = (float)T;
+  a.sr_c = (float)(1.0 / (2.0 * tanh(1.0 / (2.0 * T))));
+  a.sr_invT = (float)(1.0 / T);
+  a.sigma = p.sigma;
+  a.lr = p.lr;
+  const double tt = (double)(p.t < 1 ? 1 : p.t);
+  a.bc1 = (float)(1.0 - pow(0.9, tt));
+  a.bc2 = (float)(1.0 - pow(0.999, tt));
+  a.t_lo = (unsigned)(p.t & 0xFFFFFFFFll);
+  a.mode = p.quant_mode;
+  a.upd = p.update_latents;
+  return a;
+}
+
+int check_params(const cc_step_params* p) {
+  if (!p) return fail(CC_EINVAL, "step params are NULL");
+  if (p->quant_mode != CC_SOFT && p->quant_mode != CC_HARD) return fail(CC_EINVAL, "quant_mode");
+  if (p->quant_mode == CC_SOFT && !(p->temperature > 0.0f))
+    return fail(CC_EINVAL, "temperature must be > 0");
+  if (!(p->sigma >= 0.0f) || !(p->lr >= 0.0f) || p->t < 1)
+    return fail(CC_EINVAL, "sigma, lr must be >= 0 and t >= 1");
+  return CC_OK;
+}
+
+#define RET(x)                    \
+  do {                            \
+    int r_ = (x);                 \
+    if (r_ != CC_OK) return r_ == CC_EDEVICE ? fail(CC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : r_; \
+  } while (0)
+
+int set_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st) {
+  StepLaunch sl;
+  memset(&sl, 0, sizeof sl);
+  sl.n = n;
+  for (int i = 0; i < n; ++i) {
+    sl.d[i] = s[i]->ddev;
+    sl.a[i] = step_args(p[i]);
+  }
+  return cc_launch_set_step(sl, st);
+}
+
+int arm(cc_state* const* s, int n, int bwd, hipStream_t st) {
+  const Launch l = plan(s, n, [](const DevDesc& h) { return h.arm_nwg; });
+  if (s[0]->precision == CC_BF16_FUSED && cc_arm_fused_supported(s[0]->lo.h))
+    return cc_launch_arm_fused(l, s[0]->lo.h, bwd, st);
+  return cc_launch_arm_plain(l, s[0]->lo.h, bwd, st);
+}
+
+// Forward of the distortion branch: upsampling, synthesis, residual layers
+// (+ MSE when want_mse).
+int forward_dist(cc_state* const* s, int n, int want_mse, hipStream_t st) {
+  const DevDesc& h0 = s[0]->lo.h;
+  for (int j = h0.L - 1; j >= 1; --j) {
+    const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j - 1] * h.gw[j - 1], CC_PIX_TILE); });
+    RET(cc_launch_ups_fwd(l, j, st));
+  }
+  const Launch lp = plan(s, n, [](const DevDesc& h) { return h.pix_ntile; });
+  RET(cc_launch_syn_fwd_plain(lp, h0, (h0.n_res == 0 && want_mse) ? 1 : 0, st));
+  for (int r = 0; r < h0.n_res; ++r) RET(cc_launch_res_fwd(lp, r, r == h0.n_res - 1, want_mse, st));
+  return CC_OK;
+}
+
+int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st, bool update,
+             bool backward) {
+  const DevDesc& h0 = s[0]->lo.h;
+  RET(set_step(s, n, p, st));
+  RET(cc_launch_qtrain(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st));
+  RET(arm(s, n, backward ? 1 : 0, st));
+  if (backward && h0.G > 0) {
+    for (int f = 1; f < h0.L; ++f) {
+      const Launch l = plan(s, n, [f](const DevDesc& h) {
+        long long tot = 0;
+        for (int c = 0; c < h.G; ++c)
+          if (c + f <= h.L - 1) tot += (long long)h.F * h.gh[c + f] * h.gw[c + f];
+        return cdiv(tot, CC_ELT_TILE);
+      });
+      RET(cc_launch_pool(l, f, st));
+    }
+  }
+  RET(forward_dist(s, n, 1, st));
+  if (backward) {
+    const Launch lp = plan(s, n, [](const DevDesc& h) { return h.pix_ntile; });
+    int src_b = 0;
+    for (int r = h0.n_res - 1; r >= 0; --r) {
+      RET(cc_launch_res_bwd2(lp, r, src_b, st));
+      src_b ^= 1;
+    }
+    RET(cc_launch_syn_bwd_plain(plan(s, n, [](const DevDesc& h) { return h.syn_nwg; }), h0, src_b, st));
+    for (int j = 1; j < h0.L; ++j) {
+      const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE); });
+      RET(cc_launch_ups_bwd(l, j, st));
+    }
+    RET(cc_launch_join(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st));
+    const Launch w1 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, 64) * CC_WRED_SPLIT; });
+    const Launch w2 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, CC_ELT_TILE); });
+    RET(cc_launch_wreduce(w1, w2, st));
+  }
+  Launch lr;
+  memset(&lr, 0, sizeof lr);
+  lr.n = n;
+  for (int i = 0; i < n; ++i) lr.d[i] = s[i]->ddev;
+  RET(cc_launch_lreduce(lr, st));
+  if (update) RET(cc_launch_adam(plan(s, n, [](const DevDesc& h) { return cdiv(h.n_theta, CC_ELT_TILE); }), st));
+  return CC_OK;
+}
+
+int read_scal(cc_state* s, double* out3, hipStream_t st) {
+  double sc[4];
+  HIPCHK(hipMemcpyAsync(sc, s->lo.h.scal, sizeof sc, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (out3) {
+    out3[0] = sc[0];
+    out3[1] = sc[1];
+    out3[2] = sc[2];
+  }
+  if (sc[3] != 1.0) {
+    s->nonfinite = 1;
+    return fail(CC_ENONFINITE, "non-finite loss (%g)", sc[0]);
+  }
+  return CC_OK;
+}
+
+int check_state(const cc_state* s) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  if (s->nonfinite) return fail(CC_ENONFINITE, "an earlier step produced a non-finite loss");
+  return CC_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char* cc_last_error(void) { return g_err; }
+
+int cc_config_supported(const cc_config* cfg, int H, int W) { return check_config(cfg, H, W) == CC_OK; }
+
+int64_t cc_n_latents(const cc_config* cfg, int H, int W) {
+  if (!cfg || cfg->L < 1 || cfg->L > CC_MAX_L) return -1;
+  int64_t n = 0;
+  for (int k = 0; k < cfg->L; ++k) n += (int64_t)(H >> k) * (W >> k);
+  return n;
+}
+
+int cc_n_params(const cc_config* cfg) {
+  if (check_config(cfg, 1 << (cfg ? cfg->L - 1 : 0), 1 << (cfg ? cfg->L - 1 : 0)) != CC_OK) return -1;
+  Layout lo;
+  build_layout(cfg, 1 << (cfg->L - 1), 1 << (cfg->L - 1), lo);
+  return lo.h.n_par;
+}
+
+size_t cc_state_bytes(const cc_config* cfg, int H, int W) {
+  if (check_config(cfg, H, W) != CC_OK) return 0;
+  Layout lo;
+  build_layout(cfg, H, W, lo);
+  return lo.bytes;
+}
+
+int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, double lambda,
+                  uint64_t seed, const float* init_latents_host, const float* init_params_host,
+                  void* mem, size_t bytes, void* stream, cc_state** out) {
+  if (!out) return fail(CC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_config(cfg, H, W);
+  if (rc != CC_OK) return rc;
+  if (!img_dev || !mem) return fail(CC_EINVAL, "image or slab pointer is NULL");
+  if (((uintptr_t)mem & 255) != 0) return fail(CC_EINVAL, "slab must be 256-byte aligned");
+  if (!(lambda >= 0.0) || !isfinite(lambda)) return fail(CC_EINVAL, "lambda must be finite and >= 0");
+  cc_state* s = new (std::nothrow) cc_state();
+  if (!s) return fail(CC_EINVAL, "host allocation failed");
+  s->cfg = *cfg;
+  build_layout(cfg, H, W, s->lo);
+  if (bytes < s->lo.bytes) {
+    const size_t need = s->lo.bytes;
+    delete s;
+    return fail(CC_ENOMEM, "state slab has %zu bytes, needs %zu", bytes, need);
+  }
+  s->base = (char*)mem;
+  s->precision = cfg->precision;
+  s->ddev = (DevDesc*)(s->base + s->lo.off_desc);
+  if (hipGetDevice(&s->device) != hipSuccess) s->device = -1;
+  set_pointers(s->lo, s->base);
+  DevDesc& h = s->lo.h;
+  h.lambda = (float)lambda;
+  h.rate_scale = (float)(lambda / ((double)H * W));
+  h.mse_scale = (float)(2.0 / (3.0 * (double)H * W));
+  h.seed_lo = (unsigned)(seed & 0xFFFFFFFFull);
+  h.seed_hi = (unsigned)(seed >> 32);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<float> theta(h.n_theta, 0.0f);
+  if (init_latents_host) memcpy(theta.data(), init_latents_host, sizeof(float) * h.n_lat);
+  if (init_params_host) {
+    memcpy(theta.data() + h.n_lat, init_params_host, sizeof(float) * h.n_par);
+  } else {
+    std::vector<float> P;
+    default_params(h, seed, P);
+    memcpy(theta.data() + h.n_lat, P.data(), sizeof(float) * h.n_par);
+  }
+  std::vector<float> zeros(h.n_theta, 0.0f);
+  auto cp = [&](void* dst, const void* src, size_t n) { return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st); };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = cp(s->ddev, &h, sizeof(DevDesc));
+  if (e == hipSuccess) e = hipMemcpyAsync(h.img, img_dev, sizeof(float) * 3 * (size_t)H * W, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = cp(h.theta, theta.data(), sizeof(float) * h.n_theta);
+  if (e == hipSuccess) e = cp(h.m, zeros.data(), sizeof(float) * h.n_theta);
+  if (e == hipSuccess) e = cp(h.v, zeros.data(), sizeof(float) * h.n_theta);
+  if (e == hipSuccess) e = cp(h.grad, zeros.data(), sizeof(float) * h.n_theta);
+  if (e == hipSuccess) e = cp(h.arm_gtab, s->lo.arm_gtab.data(), sizeof(unsigned) * s->lo.arm_gtab.size());
+  if (e == hipSuccess) e = cp(h.syn_gtab, s->lo.syn_gtab.data(), sizeof(unsigned) * s->lo.syn_gtab.size());
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(CC_EDEVICE, "init copies failed: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return CC_OK;
+}
+
+int cc_encode_step_batch(cc_state* const* states, int n, const cc_step_params* p, double* out,
+                         void* stream) {
+  if (!states || n < 1 || n > CC_MAX_BATCH) return fail(CC_EINVAL, "batch size %d outside [1, %d]", n, CC_MAX_BATCH);
+  for (int i = 0; i < n; ++i) {
+    int rc = check_state(states[i]);
+    if (rc != CC_OK) return rc;
+    rc = check_params(&p[i]);
+    if (rc != CC_OK) return rc;
+    if (!same_shape(states[0], states[i])) return fail(CC_EINVAL, "batch mixes decoder shapes or precisions");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  RET(run_step(states, n, p, st, true, true));
+  for (int i = 0; i < n; ++i) states[i]->t = p[i].t;
+  if (out) {
+    int worst = CC_OK;
+    for (int i = 0; i < n; ++i) {
+      const int rc = read_scal(states[i], out + 3 * i, st);
+      if (rc != CC_OK && worst == CC_OK) worst = rc;
+    }
+    return worst;
+  }
+  return CC_OK;
+}
+
+int cc_encode_step(cc_state* s, const cc_step_params* p, double* out3, void* stream) {
+  return cc_encode_step_batch(&s, 1, p, out3, stream);
+}
+
+int cc_eval_loss(cc_state* s, const cc_step_params* p, double* out3, void* stream) {
+  int rc = check_state(s);
+  if (rc != CC_OK) return rc;
+  rc = check_params(p);
+  if (rc != CC_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  RET(run_step(&s, 1, p, st, false, false));
+  double sc[4];
+  HIPCHK(hipMemcpyAsync(sc, s->lo.h.scal, sizeof sc, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (out3) memcpy(out3, sc, 3 * sizeof(double));
+  return CC_OK;
+}
+
+int cc_rd_eval(cc_state* s, cc_rd_result* out, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  cc_step_params p{};
+  p.t = 1;
+  p.quant_mode = CC_HARD;
+  p.temperature = 1.0f;
+  hipStream_t st = (hipStream_t)stream;
+  RET(run_step(&s, 1, &p, st, false, false));
+  double sc[4];
+  HIPCHK(hipMemcpyAsync(sc, s->lo.h.scal, sizeof sc, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (out) {
+    const double hw = (double)s->lo.h.H * s->lo.h.W;
+    out->loss = sc[0];
+    out->bits = sc[1];
+    out->mse = sc[2];
+    out->bpp = sc[1] / hw;
+    out->psnr = sc[2] > 0 ? 10.0 * log10(1.0 / sc[2]) : INFINITY;
+  }
+  return CC_OK;
+}
+
+int cc_decode(cc_state* s, float* out_img_dev, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  if (!out_img_dev) return fail(CC_EINVAL, "output pointer is NULL");
+  cc_step_params p{};
+  p.t = 1;
+  p.quant_mode = CC_HARD;
+  p.temperature = 1.0f;
+  hipStream_t st = (hipStream_t)stream;
+  RET(set_step(&s, 1, &p, st));
+  RET(cc_launch_qtrain(plan(&s, 1, [](const DevDesc& h) { return h.lat_ntile; }), st));
+  RET(forward_dist(&s, 1, 0, st));
+  RET(cc_launch_copy_out(plan(&s, 1, [](const DevDesc& h) { return cdiv(3 * h.H * h.W, CC_ELT_TILE); }), out_img_dev, st));
+  return CC_OK;
+}
+
+int cc_get_state(cc_state* s, float* latents, float* params, float* adam_m, float* adam_v,
+                 int64_t* t, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  if (latents) HIPCHK(hipMemcpyAsync(latents, h.theta, sizeof(float) * h.n_lat, hipMemcpyDeviceToHost, st));
+  if (params) HIPCHK(hipMemcpyAsync(params, h.theta + h.n_lat, sizeof(float) * h.n_par, hipMemcpyDeviceToHost, st));
+  if (adam_m) HIPCHK(hipMemcpyAsync(adam_m, h.m, sizeof(float) * h.n_theta, hipMemcpyDeviceToHost, st));
+  if (adam_v) HIPCHK(hipMemcpyAsync(adam_v, h.v, sizeof(float) * h.n_theta, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (t) *t = s->t;
+  return CC_OK;
+}
+
+int cc_set_state(cc_state* s, const float* latents, const float* params, const float* adam_m,
+                 const float* adam_v, int64_t t, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  if (latents) HIPCHK(hipMemcpyAsync(h.theta, latents, sizeof(float) * h.n_lat, hipMemcpyHostToDevice, st));
+  if (params) HIPCHK(hipMemcpyAsync(h.theta + h.n_lat, params, sizeof(float) * h.n_par, hipMemcpyHostToDevice, st));
+  if (adam_m) HIPCHK(hipMemcpyAsync(h.m, adam_m, sizeof(float) * h.n_theta, hipMemcpyHostToDevice, st));
+  if (adam_v) HIPCHK(hipMemcpyAsync(h.v, adam_v, sizeof(float) * h.n_theta, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  s->t = t;
+  s->nonfinite = 0;
+  return CC_OK;
+}
+
+int cc_get_grad(cc_state* s, float* grad_host, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  if (!grad_host) return fail(CC_EINVAL, "grad pointer is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(grad_host, s->lo.h.grad, sizeof(float) * s->lo.h.n_theta, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CC_OK;
+}
+
+int cc_set_precision(cc_state* s, int precision) {
+  if (!s) return fail(CC_ESTATE, "state not initialised");
+  if (precision != CC_FP32_PLAIN && precision != CC_BF16_FUSED) return fail(CC_EINVAL, "precision=%d", precision);
+  s->precision = precision;
+  return CC_OK;
+}
+
+void cc_free_state(cc_state* s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal definitions shared by the HIP kernels and the host side of the
+// Cool-chic encode-step library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/coolchic.h"
+
+#define CC_MAX_L 8
+#define CC_MAX_S 32
+#define CC_MAX_PROD 16
+
+// One producer of weight-gradient partial rows (a kernel whose workgroups
+// each write the sum of their positions' contributions to a parameter range).
+struct ProdSeg {
+  int pbeg;      // first parameter index (within the decoder parameters)
+  int pcnt;      // number of parameters
+  int nrows;     // partial rows (one per producing workgroup)
+  int pad;
+  long long off; // float offset of row 0 in the partial buffer; row stride pcnt
+};
+
+// Per-image descriptor, resident in device memory at the start of the state
+// slab; kernels read it through uniform (scalar) loads.
+struct DevDesc {
+  // ---- shape
+  int H, W, L, S, F, G, H1, H2, ctx, arm_stab, syn_stab, n_syn_hidden, n_res;
+  int syn_w[4];                 // L, hidden..., 3 (n_syn_hidden + 2 entries)
+  int n_lat, n_par, n_theta;
+  int goff[CC_MAX_L], gh[CC_MAX_L], gw[CC_MAX_L];
+  int uoff[CC_MAX_L];           // U_j (j >= 1): (L-j) channels at grid j-1
+  int dfoff[4][CC_MAX_L];       // IFCE df pyramid of child grid c at level f
+  int dy[CC_MAX_S], dx[CC_MAX_S];
+  // ---- parameter offsets (within the decoder parameters)
+  int p_aw[3], p_ab[3], p_asw, p_asb, p_iw[4], p_ib[4], p_ups[CC_MAX_L];
+  int p_sw[3], p_sb[3], p_ssw, p_ssb, p_rw[4], p_rb[4];
+  int n_arm_par;                // ARM + IFCE parameters: [0, n_arm_par)
+  // ---- scalars
+  float lambda, rate_scale, mse_scale, lmin, lmax, pmin, bits_max;
+  unsigned seed_lo, seed_hi;
+  // ---- per-step scalars (written by the set_step kernel)
+  float T, sr_c, sr_invT, sigma, lr, bc1, bc2;
+  unsigned t_lo;
+  int mode, upd;
+  // ---- producer geometry
+  int arm_nchunk, arm_nwg, syn_nchunk, syn_nwg, pix_nwg, nprod;
+  int lat_ntile, pix_ntile;
+  ProdSeg prod[CC_MAX_PROD];
+  int prod_arm, prod_syn, prod_res0, prod_ups1;   // producer indices
+  // ---- buffers (device pointers inside the slab)
+  float *img, *theta, *m, *v, *grad, *yhat, *dq, *dc, *df, *dyd, *dyq;
+  float *U, *dU, *X, *dXa, *dXb, *wp;
+  double* wp2;
+  unsigned* arm_gtab;
+  unsigned* syn_gtab;
+  double *lp_bits, *lp_mse, *scal;
+};
+
+// Kernel argument describing one batched launch: blockIdx.x in
+// [tile0[i], tile0[i+1]) belongs to image i.
+struct Launch {
+  int n;
+  int tile0[CC_MAX_BATCH + 1];
+  const DevDesc* d[CC_MAX_BATCH];
+};
+
+struct StepArgs {
+  float T, sr_c, sr_invT, sigma, lr, bc1, bc2;
+  unsigned t_lo;
+  int mode, upd;
+};
+struct StepLaunch {
+  int n;
+  DevDesc* d[CC_MAX_BATCH];
+  StepArgs a[CC_MAX_BATCH];
+};
+
+__device__ __forceinline__ int cc_find_img(const Launch& L, int b) {
+  int i = 0;
+  while (i + 1 < L.n && b >= L.tile0[i + 1]) ++i;
+  return i;
+}
+
+// -------------------------------------------------------------- host side
+// Launchers implemented in the kernel translation units.
+struct HostImg;  // defined in cc_api.hip
+int cc_launch_set_step(const StepLaunch& s, hipStream_t st);
+int cc_launch_qtrain(const Launch& l, hipStream_t st);
+int cc_launch_arm(const Launch& l, const DevDesc& h, int bwd, int precision, hipStream_t st);
+int cc_launch_pool(const Launch& l, int f, hipStream_t st);
+int cc_launch_join(const Launch& l, hipStream_t st);
+int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st);
+int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st);
+int cc_launch_syn_fwd(const Launch& l, const DevDesc& h, int final_mse, int precision, hipStream_t st);
+int cc_launch_syn_bwd(const Launch& l, const DevDesc& h, int precision, hipStream_t st);
+int cc_launch_res_fwd(const Launch& l, int r, int last, int want_mse, hipStream_t st);
+int cc_launch_res_bwd(const Launch& l, int r, hipStream_t st);
+int cc_launch_wreduce(const Launch& l1, const Launch& l2, hipStream_t st);
+int cc_launch_lreduce(const Launch& l, hipStream_t st);
+int cc_launch_adam(const Launch& l, hipStream_t st);
+int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
+
+// Tile geometry shared by host launch planning and kernels.
+#define CC_ELT_TILE 256     // elementwise kernels: threads per block
+#define CC_ARM_CHUNK 64     // ARM kernel: positions per chunk (= threads per block)
+#define CC_ARM_CPW 4        // ARM kernel: chunks per workgroup
+#define CC_SYN_CHUNK 64
+#define CC_SYN_CPW 4
+#define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
+#define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1

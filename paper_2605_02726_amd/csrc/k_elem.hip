@@ -1,0 +1,285 @@
+// Elementwise and reduction kernels of the encode step: per-step scalars,
+// training quantisation proxy with in-kernel Philox noise, IFCE gradient
+// pyramid, the join of all latent gradients, deterministic reductions and
+// Adam.
+#include "cc_internal.h"
+
+#include <math.h>
+
+namespace {
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplies with the key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox10(uint4 c, unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const unsigned lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const unsigned lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// Box-Muller on the top 24 bits of two words; u1 is never zero.
+__device__ __forceinline__ float gauss(unsigned r0, unsigned r1) {
+  const float u1 = ((float)(r0 >> 8) + 0.5f) * 5.9604644775390625e-8f;
+  const float u2 = (float)(r1 >> 8) * 5.9604644775390625e-8f;
+  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+// Softround s_T (Section IV-C, eq. softround) and its derivative;
+// c = 1 / (2 tanh(1 / 2T)), invT = 1 / T.
+__device__ __forceinline__ float softround(float x, float c, float invT) {
+  const float fl = floorf(x);
+  return fl + tanhf((x - fl - 0.5f) * invT) * c + 0.5f;
+}
+__device__ __forceinline__ float dsoftround(float x, float c, float invT) {
+  const float fl = floorf(x);
+  const float th = tanhf((x - fl - 0.5f) * invT);
+  return invT * (1.0f - th * th) * c;
+}
+
+__device__ __forceinline__ int grid_of(const DevDesc* d, int i) {
+  int k = 0;
+  while (k + 1 < d->L && i >= d->goff[k + 1]) ++k;
+  return k;
+}
+
+__global__ void k_set_step(StepLaunch s) {
+  const int i = threadIdx.x;
+  if (i >= s.n) return;
+  DevDesc* d = s.d[i];
+  const StepArgs a = s.a[i];
+  d->T = a.T;
+  d->sr_c = a.sr_c;
+  d->sr_invT = a.sr_invT;
+  d->sigma = a.sigma;
+  d->lr = a.lr;
+  d->bc1 = a.bc1;
+  d->bc2 = a.bc2;
+  d->t_lo = a.t_lo;
+  d->mode = a.mode;
+  d->upd = a.upd;
+}
+
+// yhat = s_T(s_T(y) + sigma n) with n from Philox counter (t, k, i, 0), and
+// d yhat / d y; or yhat = rint(y) with a straight-through derivative of 1.
+__global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L) {
+  const int im = cc_find_img(L, blockIdx.x);
+  const DevDesc* d = L.d[im];
+  const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  if (i >= d->n_lat) return;
+  const float y = d->theta[i];
+  float yh, dq;
+  if (d->mode == CC_HARD) {
+    yh = rintf(y);
+    dq = 1.0f;
+  } else {
+    const int k = grid_of(d, i);
+    const uint4 r = philox10(make_uint4(d->t_lo, (unsigned)k, (unsigned)(i - d->goff[k]), 0u),
+                             d->seed_lo, d->seed_hi);
+    const float n = gauss(r.x, r.y);
+    const float c = d->sr_c, iT = d->sr_invT;
+    const float a = softround(y, c, iT);
+    const float u = a + d->sigma * n;
+    yh = softround(u, c, iT);
+    dq = dsoftround(u, c, iT) * dsoftround(y, c, iT);
+  }
+  d->yhat[i] = yh;
+  d->dq[i] = dq;
+}
+
+// One 2x2 sum-pooling level of the IFCE gradient pyramid: level f of child
+// grid c (at grid c+f) from level f-1 (at grid c+f-1), F channels.
+__global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L, int f) {
+  const int im = cc_find_img(L, blockIdx.x);
+  const DevDesc* d = L.d[im];
+  int e = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  for (int c = 0; c < d->G; ++c) {
+    if (c + f > d->L - 1) continue;
+    const int h = d->gh[c + f], w = d->gw[c + f], n = h * w;
+    const int tot = d->F * n;
+    if (e < tot) {
+      const int ch = e / n, p = e - ch * n, y = p / w, x = p - y * w;
+      const int w0 = d->gw[c + f - 1], n0 = d->gh[c + f - 1] * w0;
+      const float* src = d->df + d->dfoff[c][f - 1] + ch * n0;
+      const float s = (src[(2 * y) * w0 + 2 * x] + src[(2 * y) * w0 + 2 * x + 1]) +
+                      (src[(2 * y + 1) * w0 + 2 * x] + src[(2 * y + 1) * w0 + 2 * x + 1]);
+      d->df[d->dfoff[c][f] + ch * n + p] = s;
+      return;
+    }
+    e -= tot;
+  }
+}
+
+// Gradient of the loss with respect to every latent y:
+//   (d rate / d yhat + d distortion / d yhat) * d yhat / d y
+// where d rate / d yhat gathers, in a fixed order, the direct term, the
+// context gradients of the positions that use this latent as a causal
+// neighbour (reversed offsets) and the IFCE gradients of finer grids.
+__global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L) {
+  const int im = cc_find_img(L, blockIdx.x);
+  const DevDesc* d = L.d[im];
+  const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  if (i >= d->n_lat) return;
+  const int k = grid_of(d, i);
+  const int h = d->gh[k], w = d->gw[k], li = i - d->goff[k];
+  const int y = li / w, x = li - y * w;
+  float g = d->dyd[i];
+  const float* dc = d->dc + d->goff[k];
+  for (int m = 0; m < d->S; ++m) {
+    const int sy = y - d->dy[m], sx = x - d->dx[m];
+    if (sy >= 0 && sy < h && sx >= 0 && sx < w) g += dc[(size_t)m * d->n_lat + sy * w + sx];
+  }
+  const float* P = d->theta + d->n_lat;
+  const int nk = h * w;
+  for (int c = 0; c < d->G && c < k; ++c) {
+    const float* W = P + d->p_iw[c];          // [F, L-c-1]
+    const int q = k - c - 1, nin = d->L - c - 1;
+    const float* D = d->df + d->dfoff[c][k - c];
+    for (int f = 0; f < d->F; ++f) g += W[f * nin + q] * D[f * nk + li];
+  }
+  g += d->dyq[i];
+  d->grad[i] = g * d->dq[i];
+}
+
+// Adam (Kingma and Ba) over theta = [latents, parameters]; latents are left
+// untouched when frozen.
+__global__ __launch_bounds__(CC_ELT_TILE) void k_adam(Launch L) {
+  const int im = cc_find_img(L, blockIdx.x);
+  const DevDesc* d = L.d[im];
+  const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  if (i >= d->n_theta) return;
+  if (i < d->n_lat && !d->upd) return;
+  const float g = d->grad[i];
+  const float m = 0.9f * d->m[i] + 0.1f * g;
+  const float v = 0.999f * d->v[i] + 0.001f * (g * g);
+  d->m[i] = m;
+  d->v[i] = v;
+  const float mh = m / d->bc1, vh = v / d->bc2;
+  d->theta[i] -= d->lr * mh / (sqrtf(vh) + 1e-8f);
+}
+
+__device__ __forceinline__ double block_sum_256(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// FP64 totals of one image in a fixed order: scal = (loss, bits, mse, finite).
+__global__ __launch_bounds__(256) void k_lreduce(Launch L) {
+  __shared__ double sh[256];
+  const DevDesc* d = L.d[blockIdx.x];
+  double b = 0.0, m = 0.0;
+  for (int r = threadIdx.x; r < d->arm_nwg; r += 256) b += d->lp_bits[r];
+  const double bits = block_sum_256(b, sh);
+  __syncthreads();
+  for (int r = threadIdx.x; r < d->pix_nwg; r += 256) m += d->lp_mse[r];
+  const double sq = block_sum_256(m, sh);
+  if (threadIdx.x == 0) {
+    const double mse = sq / (3.0 * d->H * d->W);
+    const double loss = mse + (double)d->lambda * bits / ((double)d->H * d->W);
+    d->scal[0] = loss;
+    d->scal[1] = bits;
+    d->scal[2] = mse;
+    d->scal[3] = isfinite(loss) ? 1.0 : 0.0;
+  }
+}
+
+// Weight-gradient reduction, pass 1: block (param block of 64, row split s)
+// sums its share of every producer's partial rows in FP64, fixed order.
+__global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
+  __shared__ double sh[4][64];
+  const int im = cc_find_img(L, blockIdx.x);
+  const DevDesc* d = L.d[im];
+  const int b = blockIdx.x - L.tile0[im];
+  const int pb = b / CC_WRED_SPLIT, s = b - pb * CC_WRED_SPLIT;
+  const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
+  const int p = pb * 64 + lane;
+  double acc = 0.0;
+  if (p < d->n_par) {
+    int q = 0;
+    while (q < d->nprod && !(p >= d->prod[q].pbeg && p < d->prod[q].pbeg + d->prod[q].pcnt)) ++q;
+    if (q < d->nprod) {
+      const ProdSeg g = d->prod[q];
+      const int per = (g.nrows + CC_WRED_SPLIT - 1) / CC_WRED_SPLIT;
+      const int r0 = s * per, r1 = min(g.nrows, r0 + per);
+      const float* base = d->wp + g.off + (p - g.pbeg);
+      for (int r = r0 + sub; r < r1; r += 4) acc += (double)base[(size_t)r * g.pcnt];
+    }
+  }
+  sh[sub][lane] = acc;
+  __syncthreads();
+  if (sub == 0 && p < d->n_par)
+    d->wp2[(size_t)s * d->n_par + p] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+}
+
+// Pass 2: gradient of decoder parameter p = sum of the row splits.
+__global__ __launch_bounds__(CC_ELT_TILE) void k_wreduce2(Launch L) {
+  const int im = cc_find_img(L, blockIdx.x);
+  const DevDesc* d = L.d[im];
+  const int p = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  if (p >= d->n_par) return;
+  double acc = 0.0;
+  for (int s = 0; s < CC_WRED_SPLIT; ++s) acc += d->wp2[(size_t)s * d->n_par + p];
+  d->grad[d->n_lat + p] = (float)acc;
+}
+
+__global__ __launch_bounds__(CC_ELT_TILE) void k_copy_out(Launch L, float* out) {
+  const int im = cc_find_img(L, blockIdx.x);
+  const DevDesc* d = L.d[im];
+  const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  const int n = 3 * d->H * d->W;
+  if (i >= n) return;
+  out[i] = d->X[(size_t)d->n_res * n + i];
+}
+
+inline int check_launch() {
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EDEVICE;
+}
+
+}  // namespace
+
+int cc_launch_set_step(const StepLaunch& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, st, s);
+  return check_launch();
+}
+int cc_launch_qtrain(const Launch& l, hipStream_t st) {
+  hipLaunchKernelGGL(k_qtrain, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l);
+  return check_launch();
+}
+int cc_launch_pool(const Launch& l, int f, hipStream_t st) {
+  if (l.tile0[l.n] == 0) return CC_OK;
+  hipLaunchKernelGGL(k_pool, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, f);
+  return check_launch();
+}
+int cc_launch_join(const Launch& l, hipStream_t st) {
+  hipLaunchKernelGGL(k_join, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l);
+  return check_launch();
+}
+int cc_launch_adam(const Launch& l, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l);
+  return check_launch();
+}
+int cc_launch_lreduce(const Launch& l, hipStream_t st) {
+  hipLaunchKernelGGL(k_lreduce, dim3(l.n), dim3(256), 0, st, l);
+  return check_launch();
+}
+int cc_launch_wreduce(const Launch& l1, const Launch& l2, hipStream_t st) {
+  hipLaunchKernelGGL(k_wreduce1, dim3(l1.tile0[l1.n]), dim3(256), 0, st, l1);
+  if (check_launch() != CC_OK) return CC_EDEVICE;
+  hipLaunchKernelGGL(k_wreduce2, dim3(l2.tile0[l2.n]), dim3(CC_ELT_TILE), 0, st, l2);
+  return check_launch();
+}
+int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_out, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, out);
+  return check_launch();
+}

@@ -1,0 +1,79 @@
+"""The C-ABI library loads on the host, exports every function that
+include/coolchic.h declares, and its host-only size/shape logic agrees with
+the documented layouts.  No device calls."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2605_02726_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2605_02726_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2605_02726_amd import build
+        build.build()
+    return _lib
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(cc_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    so = C.CDLL(lib.LIB_PATH)
+    missing = [n for n in names if not hasattr(so, n)]
+    assert not missing, missing
+    # and the binding covers all of them
+    assert set(names) <= set(lib.EXPORTED)
+
+
+@pytest.mark.parametrize("mk", [wl.config_small, wl.config_hop, wl.config_tiny])
+def test_param_and_latent_counts(lib, mk):
+    mc = mk()
+    cfg = lib.make_config(mc)
+    L = lib.lib()
+    assert L.cc_n_params(C.byref(cfg)) == wl.n_params(mc)
+    assert L.cc_n_latents(C.byref(cfg), 512, 768) == wl.n_latents(mc, 512, 768)
+    assert L.cc_state_bytes(C.byref(cfg), 512, 768) > 0
+
+
+def test_rejects_bad_shapes(lib):
+    L = lib.lib()
+    mc = wl.config_hop()
+    cfg = lib.make_config(mc)
+    assert L.cc_config_supported(C.byref(cfg), 512, 768) == 1
+    assert L.cc_config_supported(C.byref(cfg), 500, 768) == 0       # not a multiple of 64
+    assert "multiples" in L.cc_last_error().decode()
+    assert L.cc_state_bytes(C.byref(cfg), 0, 768) == 0
+    bad = lib.make_config(mc)
+    bad.n_spatial = 23                                              # shape not compiled in
+    assert L.cc_config_supported(C.byref(bad), 512, 768) == 0
+    bad = lib.make_config(mc)
+    bad.p_min = 0.0
+    assert L.cc_config_supported(C.byref(bad), 512, 768) == 0
+
+
+def test_state_calls_reject_null(lib):
+    L = lib.lib()
+    assert L.cc_rd_eval(None, None, None) == lib.CC_ESTATE
+    assert L.cc_encode_step(None, None, None, None) == lib.CC_ESTATE
+    out = C.c_void_p()
+    cfg = lib.make_config(wl.config_small())
+    rc = L.cc_init_state(C.byref(cfg), 64, 64, None, 1e-3, 1, None, None, None, 0, None,
+                         C.byref(out))
+    assert rc == lib.CC_EINVAL and not out.value
