@@ -144,8 +144,24 @@ int cc_set_state(cc_state* s, const float* latents, const float* params,
 /* Gradient of the last cc_encode_step (n_latents + n_params floats). */
 int cc_get_grad(cc_state* s, float* grad_host, void* stream);
 
+/* Diagnostics: copy `count` floats of an internal buffer of the last step
+ * to the host: "yhat" (quantised latents), "dq" (d yhat / d y), "dyd"
+ * (direct rate gradient), "dyq" (distortion gradient of the latents),
+ * "xhat" (decoded image), "dx0" (gradient at the synthesis trunk output).
+ * Synchronises `stream`. */
+int cc_debug_read(cc_state* s, const char* buffer, float* host, int64_t count, void* stream);
+
 /* Switch the arithmetic of the MLP kernels (CC_FP32_PLAIN / CC_BF16_FUSED). */
 int cc_set_precision(cc_state* s, int precision);
+
+/* Live kernel timing for measurement tools: HIP events are recorded on the
+ * launch stream around every launch of one kernel class ("arm", "syn_bwd",
+ * "ups_bwd", "join", "adam"; NULL or "" switches timing off) by the calls
+ * that follow.  cc_timing_read waits for those events and returns the summed
+ * duration (ms) and the number of timed launches, then resets the record.
+ * Process-wide, not thread-safe. */
+int cc_timing_enable(const char* kernel);
+int cc_timing_read(double* total_ms, int* count);
 
 void cc_free_state(cc_state* s);
 const char* cc_last_error(void);

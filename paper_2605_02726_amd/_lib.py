@@ -68,6 +68,9 @@ _PROTOS = [
                                C.c_int64, C.c_void_p]),
     ("cc_get_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cc_set_precision", C.c_int, [C.c_void_p, C.c_int]),
+    ("cc_debug_read", C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    ("cc_timing_enable", C.c_int, [C.c_char_p]),
+    ("cc_timing_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     ("cc_free_state", None, [C.c_void_p]),
     ("cc_last_error", C.c_char_p, []),
 ]

@@ -458,8 +458,44 @@ int set_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st)
   return cc_launch_set_step(sl, st);
 }
 
+// Optional live timing of one kernel class with HIP events recorded on the
+// launch stream around each of its launches (see cc_timing_enable).
+enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_ADAM = 3, TK_UPS_BWD = 4, TK_JOIN = 5 };
+struct Timing {
+  int kind = TK_NONE;
+  std::vector<hipEvent_t> ev;   // pairs (start, stop)
+  size_t used = 0;
+};
+Timing g_timing;
+
+struct TimeScope {
+  hipStream_t st;
+  bool on;
+  hipEvent_t e1 = nullptr;
+  TimeScope(int kind, hipStream_t s) : st(s), on(g_timing.kind == kind) {
+    if (!on) return;
+    if (g_timing.used + 2 > g_timing.ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          on = false;
+          return;
+        }
+        g_timing.ev.push_back(e);
+      }
+    }
+    (void)hipEventRecord(g_timing.ev[g_timing.used], st);
+    e1 = g_timing.ev[g_timing.used + 1];
+    g_timing.used += 2;
+  }
+  ~TimeScope() {
+    if (on) (void)hipEventRecord(e1, st);
+  }
+};
+
 int arm(cc_state* const* s, int n, int bwd, hipStream_t st) {
   const Launch l = plan(s, n, [](const DevDesc& h) { return h.arm_nwg; });
+  TimeScope ts(bwd ? TK_ARM : TK_NONE, st);
   if (s[0]->precision == CC_BF16_FUSED && cc_arm_fused_supported(s[0]->lo.h))
     return cc_launch_arm_fused(l, s[0]->lo.h, bwd, st);
   return cc_launch_arm_plain(l, s[0]->lo.h, bwd, st);
@@ -504,12 +540,21 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
       RET(cc_launch_res_bwd2(lp, r, src_b, st));
       src_b ^= 1;
     }
-    RET(cc_launch_syn_bwd_plain(plan(s, n, [](const DevDesc& h) { return h.syn_nwg; }), h0, src_b, st));
-    for (int j = 1; j < h0.L; ++j) {
-      const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE); });
-      RET(cc_launch_ups_bwd(l, j, st));
+    {
+      TimeScope ts(TK_SYN_BWD, st);
+      RET(cc_launch_syn_bwd_plain(plan(s, n, [](const DevDesc& h) { return h.syn_nwg; }), h0, src_b, st));
     }
-    RET(cc_launch_join(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st));
+    {
+      TimeScope ts(TK_UPS_BWD, st);
+      for (int j = 1; j < h0.L; ++j) {
+        const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE); });
+        RET(cc_launch_ups_bwd(l, j, st));
+      }
+    }
+    {
+      TimeScope ts(TK_JOIN, st);
+      RET(cc_launch_join(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st));
+    }
     const Launch w1 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, 64) * CC_WRED_SPLIT; });
     const Launch w2 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, CC_ELT_TILE); });
     RET(cc_launch_wreduce(w1, w2, st));
@@ -519,7 +564,10 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
   lr.n = n;
   for (int i = 0; i < n; ++i) lr.d[i] = s[i]->ddev;
   RET(cc_launch_lreduce(lr, st));
-  if (update) RET(cc_launch_adam(plan(s, n, [](const DevDesc& h) { return cdiv(h.n_theta, CC_ELT_TILE); }), st));
+  if (update) {
+    TimeScope ts(TK_ADAM, st);
+    RET(cc_launch_adam(plan(s, n, [](const DevDesc& h) { return cdiv(h.n_theta, CC_ELT_TILE); }), st));
+  }
   return CC_OK;
 }
 
@@ -600,7 +648,7 @@ int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, doub
   if (hipGetDevice(&s->device) != hipSuccess) s->device = -1;
   set_pointers(s->lo, s->base);
   DevDesc& h = s->lo.h;
-  h.lambda = (float)lambda;
+  h.lambda = lambda;
   h.rate_scale = (float)(lambda / ((double)H * W));
   h.mse_scale = (float)(2.0 / (3.0 * (double)H * W));
   h.seed_lo = (unsigned)(seed & 0xFFFFFFFFull);
@@ -752,10 +800,59 @@ int cc_get_grad(cc_state* s, float* grad_host, void* stream) {
   return CC_OK;
 }
 
+int cc_debug_read(cc_state* s, const char* buffer, float* host, int64_t count, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  if (!buffer || !host || count < 0) return fail(CC_EINVAL, "bad arguments");
+  const DevDesc& h = s->lo.h;
+  const float* src = nullptr;
+  int64_t n = 0;
+  if (!strcmp(buffer, "yhat")) { src = h.yhat; n = h.n_lat; }
+  else if (!strcmp(buffer, "dq")) { src = h.dq; n = h.n_lat; }
+  else if (!strcmp(buffer, "dyd")) { src = h.dyd; n = h.n_lat; }
+  else if (!strcmp(buffer, "dyq")) { src = h.dyq; n = h.n_lat; }
+  else if (!strcmp(buffer, "xhat")) { src = h.X + (size_t)h.n_res * 3 * h.H * h.W; n = 3ll * h.H * h.W; }
+  else if (!strcmp(buffer, "dx0")) { src = (h.n_res % 2) ? h.dXb : h.dXa; n = 3ll * h.H * h.W; }
+  else return fail(CC_EINVAL, "unknown buffer '%s'", buffer);
+  if (count > n) return fail(CC_EINVAL, "buffer '%s' holds %lld values", buffer, (long long)n);
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(host, src, sizeof(float) * count, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CC_OK;
+}
+
 int cc_set_precision(cc_state* s, int precision) {
   if (!s) return fail(CC_ESTATE, "state not initialised");
   if (precision != CC_FP32_PLAIN && precision != CC_BF16_FUSED) return fail(CC_EINVAL, "precision=%d", precision);
   s->precision = precision;
+  return CC_OK;
+}
+
+int cc_timing_enable(const char* kernel) {
+  int k = TK_NONE;
+  if (kernel && !strcmp(kernel, "arm")) k = TK_ARM;
+  else if (kernel && !strcmp(kernel, "syn_bwd")) k = TK_SYN_BWD;
+  else if (kernel && !strcmp(kernel, "adam")) k = TK_ADAM;
+  else if (kernel && !strcmp(kernel, "ups_bwd")) k = TK_UPS_BWD;
+  else if (kernel && !strcmp(kernel, "join")) k = TK_JOIN;
+  else if (kernel && kernel[0]) return fail(CC_EINVAL, "unknown kernel class '%s'", kernel);
+  g_timing.kind = k;
+  g_timing.used = 0;
+  return CC_OK;
+}
+
+int cc_timing_read(double* total_ms, int* count) {
+  double tot = 0.0;
+  int n = 0;
+  for (size_t i = 0; i + 1 < g_timing.used; i += 2) {
+    HIPCHK(hipEventSynchronize(g_timing.ev[i + 1]));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, g_timing.ev[i], g_timing.ev[i + 1]));
+    tot += ms;
+    ++n;
+  }
+  if (total_ms) *total_ms = tot;
+  if (count) *count = n;
+  g_timing.used = 0;
   return CC_OK;
 }
 

@@ -37,7 +37,8 @@ struct DevDesc {
   int p_sw[3], p_sb[3], p_ssw, p_ssb, p_rw[4], p_rb[4];
   int n_arm_par;                // ARM + IFCE parameters: [0, n_arm_par)
   // ---- scalars
-  float lambda, rate_scale, mse_scale, lmin, lmax, pmin, bits_max;
+  double lambda;
+  float rate_scale, mse_scale, lmin, lmax, pmin, bits_max;
   unsigned seed_lo, seed_hi;
   // ---- per-step scalars (written by the set_step kernel)
   float T, sr_c, sr_invT, sigma, lr, bc1, bc2;

@@ -24,11 +24,19 @@ __device__ __forceinline__ uint4 philox10(uint4 c, unsigned k0, unsigned k1) {
   return c;
 }
 
-// Box-Muller on the top 24 bits of two words; u1 is never zero.
+// Box-Muller on the top 24 bits of two words: u1 = (k + 1/2) 2^-24 with
+// k = r0 >> 8 (never zero), u2 = (r1 >> 8) 2^-24.  k + 1/2 needs 25 bits when
+// k >= 2^23, so there ln(u1) is taken as log1p(-(1 - u1)) with
+// 1 - u1 = (2^24 - 1/2 - k) 2^-24, which is exact in FP32 on that half.
 __device__ __forceinline__ float gauss(unsigned r0, unsigned r1) {
-  const float u1 = ((float)(r0 >> 8) + 0.5f) * 5.9604644775390625e-8f;
+  const unsigned k = r0 >> 8;
+  float lnu1;
+  if (k >= (1u << 23))
+    lnu1 = log1pf(-((float)(0xFFFFFFu - k) + 0.5f) * 5.9604644775390625e-8f);
+  else
+    lnu1 = logf(((float)k + 0.5f) * 5.9604644775390625e-8f);
   const float u2 = (float)(r1 >> 8) * 5.9604644775390625e-8f;
-  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+  return sqrtf(-2.0f * lnu1) * cospif(2.0f * u2);
 }
 
 // Softround s_T (Section IV-C, eq. softround) and its derivative;
@@ -37,10 +45,14 @@ __device__ __forceinline__ float softround(float x, float c, float invT) {
   const float fl = floorf(x);
   return fl + tanhf((x - fl - 0.5f) * invT) * c + 0.5f;
 }
+// 1 - tanh^2(a) written as 4 e / (1 + e)^2 with e = exp(-2 |a|): no
+// cancellation where tanh saturates near the half-integers.
 __device__ __forceinline__ float dsoftround(float x, float c, float invT) {
   const float fl = floorf(x);
-  const float th = tanhf((x - fl - 0.5f) * invT);
-  return invT * (1.0f - th * th) * c;
+  const float a = fabsf((x - fl - 0.5f) * invT);
+  const float e = expf(-2.0f * a);
+  const float q = 1.0f + e;
+  return invT * c * (4.0f * e / (q * q));
 }
 
 __device__ __forceinline__ int grid_of(const DevDesc* d, int i) {
@@ -186,7 +198,7 @@ __global__ __launch_bounds__(256) void k_lreduce(Launch L) {
   const double sq = block_sum_256(m, sh);
   if (threadIdx.x == 0) {
     const double mse = sq / (3.0 * d->H * d->W);
-    const double loss = mse + (double)d->lambda * bits / ((double)d->H * d->W);
+    const double loss = mse + d->lambda * bits / ((double)d->H * d->W);
     d->scal[0] = loss;
     d->scal[1] = bits;
     d->scal[2] = mse;

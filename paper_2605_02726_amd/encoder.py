@@ -153,6 +153,11 @@ class Encoder:
                 for a in (latents, params, m, v)]
         check(lib().cc_set_state(self.handle, *[_ptr(a) for a in arrs], int(t), _stream()))
 
+    def debug_read(self, name: str, count: int) -> np.ndarray:
+        out = np.empty(count, np.float32)
+        check(lib().cc_debug_read(self.handle, name.encode(), _ptr(out), count, _stream()))
+        return out
+
     def grad(self) -> np.ndarray:
         g = np.empty(self.n_lat + self.n_par, np.float32)
         check(lib().cc_get_grad(self.handle, _ptr(g), _stream()))

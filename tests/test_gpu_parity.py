@@ -2,7 +2,11 @@
 
 Rule (per element, per step from the same state): |gpu - oracle| <=
 rtol |oracle| + rtol rms(oracle over the tensor), rtol = 1e-5; loss, bits and
-MSE totals within 1e-5 relative.
+MSE totals within 1e-5 relative.  A ReLU, clamp or probability-floor
+decision whose argument lies within rounding of its threshold may go either
+way in FP32: the oracle recomputes the gradient with each such decision
+inverted on its own, and the sum of the resulting changes is added to the
+tolerance of each element (decision_slack).
 """
 import numpy as np
 import pytest
@@ -11,7 +15,7 @@ import torch
 from oracle import coolchic_ref as R
 from paper_2605_02726_amd import workloads as wl
 
-from gpu_util import mixed_excess, segments
+from gpu_util import decision_slack, outliers, segments, slack_outliers
 
 pytestmark = pytest.mark.gpu
 
@@ -61,15 +65,18 @@ def test_first_step_gradient_and_totals(case, quant):
     assert loss == pytest.approx(ref[0], rel=RTOL)
     assert bits == pytest.approx(ref[1], rel=RTOL)
     assert mse == pytest.approx(ref[2], rel=RTOL)
-    gref = ref[3].copy()
-    if quant == "hard":
-        # latents are not trained in the hard stage; their straight-through
-        # gradient is still produced and compared
-        pass
-    ratio, name, idx = mixed_excess(g, gref, RTOL, segments(mc, H, W))
-    print(f"[{case}/{quant}] gradient worst ratio {ratio:.3f} at {name}[{idx}]: "
-          f"{g[idx]:.9g} vs {gref[idx]:.9g}", flush=True)
-    assert ratio <= 1.0
+    gref = ref[3]
+    theta = np.concatenate([lat, par]).astype(np.float64)
+    n_plain, worst = outliers(g, gref, RTOL, segments(mc, H, W))
+    n_bad, n_near, n_used = 0, 0, 0
+    if n_plain:   # only then are the decision slacks needed
+        _, slack, n_near, n_used = decision_slack(mc, H, W, theta, img, lam, quant, T, sigma,
+                                                  seed, t)
+        n_bad, worst = slack_outliers(g, gref, slack, RTOL, segments(mc, H, W))
+    print(f"[{case}/{quant}] gradient: {n_plain} of {g.size} outside the plain rule; {n_near} "
+          f"near-threshold decisions ({n_used} flipped one by one); {n_bad} outside with their "
+          f"slack; worst {worst}", flush=True)
+    assert n_bad == 0
 
 
 @pytest.mark.parametrize("case", ["small_random", "hop_128x192_random"])
@@ -88,18 +95,33 @@ def test_adam_update_matches_oracle(case):
     got = np.concatenate([st["latents"], st["params"]]).astype(np.float64)
     g = ost.last_grad
     segs = segments(mc, H, W)
+    # gradient tolerance per element (rule + decision slack), then its image
+    # through the first Adam step lr g / (|g| + eps), plus FP32 rounding of
+    # the update; where the tolerance reaches |g| the sign itself is open
     tol = np.zeros_like(g)
     for _, sl in segs:
         rms = np.sqrt(np.mean(g[sl] ** 2))
         tol[sl] = RTOL * (np.abs(g[sl]) + rms)
-    ambiguous = np.abs(g) <= 10 * tol
+    eps = 1e-8
+    open_sign = tol >= np.abs(g)
+    _, slack, _, _ = decision_slack(mc, H, W, np.concatenate([lat, par]).astype(np.float64), img,
+                                    lam, "soft", 0.35, 0.22, seed, 1)
+    # a decision slack on the gradient opens the sign like a small gradient does
+    open_sign |= slack >= np.abs(g)
+    # |g/(|g|+eps) - g'/(|g'|+eps)| for same-sign g, g' with |g - g'| <= delta
+    delta = tol + slack
+    lo = np.maximum(np.abs(g) - delta, 0.0)
+    bound = np.where(open_sign, 2 * lr,
+                     lr * eps * delta / ((np.abs(g) + eps) * (lo + eps)) +
+                     2.4e-7 * (np.abs(ost.theta) + lr))
     err = np.abs(got - ost.theta)
-    bound = np.where(ambiguous, 2 * lr * 1.0001, 1e-5 * np.abs(ost.theta) + 1e-6 * lr)
-    frac = float(np.mean(ambiguous))
-    print(f"[{case}] ambiguous fraction {frac:.2e}, worst {float(np.max(err / bound)):.3f}", flush=True)
-    assert np.all(err <= bound)
-    assert frac < 1e-2
-    assert np.allclose(st["m"], ost.m, rtol=1e-4, atol=1e-4 * float(np.sqrt(np.mean(ost.m ** 2))))
+    bad = np.nonzero(err > bound)[0]
+    print(f"[{case}] open-sign fraction {float(np.mean(open_sign)):.2e}; {len(bad)} outside: "
+          f"{[(int(i), float(err[i]), float(bound[i])) for i in bad[:5]]}", flush=True)
+    assert len(bad) == 0
+    m_ref = ost.m
+    m_tol = 1e-5 * (np.abs(m_ref) + float(np.sqrt(np.mean(m_ref ** 2)))) + 0.1 * slack + 1e-12
+    assert np.all(np.abs(st["m"] - m_ref) <= m_tol)
 
 
 @pytest.mark.parametrize("case", ["small_random", "hop_128x192_random", "tiny_64x32_random"])
