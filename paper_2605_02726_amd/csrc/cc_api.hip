@@ -67,8 +67,8 @@ struct Layout {
   size_t bytes = 0;
   size_t off_desc = 0, off_img, off_theta, off_m, off_v, off_grad, off_yhat, off_dq, off_dyd,
          off_dyq, off_dc, off_df, off_U, off_dU, off_X, off_dXa, off_dXb, off_wp, off_wp2,
-         off_agt, off_sgt, off_lpb, off_lpm, off_scal;
-  std::vector<unsigned> arm_gtab, syn_gtab;
+         off_agt, off_sgt, off_lpb, off_lpm, off_scal, off_aft;
+  std::vector<unsigned> arm_gtab, syn_gtab, arm_ftab;
   int syn_o[7];
 };
 
@@ -184,7 +184,12 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
 
   // producer geometry
   for (int k = 0; k < h.L; ++k) h.arm_nchunk += cdiv(h.gh[k] * h.gw[k], CC_ARM_CHUNK);
-  h.arm_nwg = cdiv(h.arm_nchunk, CC_ARM_CPW);
+  h.arm_nwg_plain = cdiv(h.arm_nchunk, CC_ARM_CPW);
+  h.arm_nwg_fused = 0;
+  for (int k = 0; k < h.L; ++k) h.arm_nwg_fused += cdiv(h.gh[k], CC_FUSED_BAND);
+  h.arm_fused = (c->precision == CC_BF16_FUSED && cc_arm_fused_supported(h)) ? 1 : 0;
+  // partial rows are sized for either form; the current one is selected below
+  h.arm_nwg = std::max(h.arm_nwg_plain, h.arm_nwg_fused);
   const int npix = H * W;
   h.syn_nchunk = cdiv(npix, CC_SYN_CHUNK);
   h.syn_nwg = cdiv(h.syn_nchunk, CC_SYN_CPW);
@@ -195,7 +200,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   int q = 0;
   h.prod_arm = q;
   h.prod[q++] = {0, h.n_arm_par, h.arm_nwg, 0, wpo};
-  wpo += (long long)h.arm_nwg * h.n_arm_par;
+  wpo += (long long)std::max(h.arm_nwg_plain, h.arm_nwg_fused) * h.n_arm_par;
   h.prod_ups1 = q;
   for (int j = 1; j < h.L; ++j) {
     const int rows = cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE);
@@ -211,6 +216,8 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
     wpo += (long long)h.pix_ntile * 84;
   }
   h.nprod = q;
+  h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
+  h.prod[h.prod_arm].nrows = h.arm_nwg;
 
   // weight-gradient tables: (index into gradient vector, index into
   // activation vector, grid requirement) per parameter, matching the LDS row
@@ -243,6 +250,38 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
       for (int f = 0; f < h.F; ++f)
         for (int qq = 0; qq < nin; ++qq) t[h.p_iw[k] + f * nin + qq] = ent(O_DF + f, O_R + qq, k);
       for (int f = 0; f < h.F; ++f) t[h.p_ib[k] + f] = ent(O_DF + f, O_ONE, k);
+    }
+  }
+  {
+    // fused ARM: parameter -> (grid requirement, accumulator, row, column)
+    auto ent = [](int k, int a, int row, int col) {
+      return ((unsigned)(k & 0xFF) << 16) | ((unsigned)a << 10) | ((unsigned)row << 5) | (unsigned)col;
+    };
+    const int CTX = h.ctx;
+    std::vector<unsigned>& t = Lo.arm_ftab;
+    t.assign(h.n_arm_par, 0xFFFFFFFFu);
+    for (int u = 0; u < h.H1; ++u) {
+      for (int q2 = 0; q2 < CTX; ++q2) t[h.p_aw[0] + u * CTX + q2] = ent(0xFF, 0, u, q2);
+      t[h.p_ab[0] + u] = ent(0xFF, 0, u, CTX);
+    }
+    for (int u = 0; u < h.H2; ++u) {
+      for (int q2 = 0; q2 < h.H1; ++q2) t[h.p_aw[1] + u * h.H1 + q2] = ent(0xFF, 1, u, q2);
+      t[h.p_ab[1] + u] = ent(0xFF, 1, u, h.H1);
+    }
+    for (int a = 0; a < 2; ++a) {
+      for (int q2 = 0; q2 < h.H2; ++q2) t[h.p_aw[2] + a * h.H2 + q2] = ent(0xFF, 2, a, q2);
+      t[h.p_ab[2] + a] = ent(0xFF, 2, a, h.H2);
+      if (h.arm_stab) {
+        for (int q2 = 0; q2 < CTX; ++q2) t[h.p_asw + a * CTX + q2] = ent(0xFF, 0, h.H1 + a, q2);
+        t[h.p_asb + a] = ent(0xFF, 0, h.H1 + a, CTX);
+      }
+    }
+    for (int k = 0; k < h.G; ++k) {
+      const int nin = h.L - k - 1;
+      for (int f = 0; f < h.F; ++f) {
+        for (int q2 = 0; q2 < nin; ++q2) t[h.p_iw[k] + f * nin + q2] = ent(k, 2, 2 + f, h.H2 + 1 + q2);
+        t[h.p_ib[k] + f] = ent(k, 2, 2 + f, h.H2);
+      }
     }
   }
   {
@@ -312,7 +351,8 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   Lo.off_wp2 = take(sizeof(double) * (size_t)CC_WRED_SPLIT * h.n_par);
   Lo.off_agt = take(sizeof(unsigned) * (size_t)h.n_arm_par);
   Lo.off_sgt = take(sizeof(unsigned) * Lo.syn_gtab.size());
-  Lo.off_lpb = take(sizeof(double) * (size_t)h.arm_nwg);
+  Lo.off_lpb = take(sizeof(double) * (size_t)std::max(h.arm_nwg_plain, h.arm_nwg_fused));
+  Lo.off_aft = take(sizeof(unsigned) * (size_t)h.n_arm_par);
   Lo.off_lpm = take(sizeof(double) * (size_t)h.pix_ntile);
   Lo.off_scal = take(sizeof(double) * 4);
   Lo.bytes = o;
@@ -339,6 +379,7 @@ void set_pointers(Layout& Lo, char* base) {
   h.wp = (float*)(base + Lo.off_wp);
   h.wp2 = (double*)(base + Lo.off_wp2);
   h.arm_gtab = (unsigned*)(base + Lo.off_agt);
+  h.arm_ftab = (unsigned*)(base + Lo.off_aft);
   h.syn_gtab = (unsigned*)(base + Lo.off_sgt);
   h.lp_bits = (double*)(base + Lo.off_lpb);
   h.lp_mse = (double*)(base + Lo.off_lpm);
@@ -496,8 +537,7 @@ struct TimeScope {
 int arm(cc_state* const* s, int n, int bwd, hipStream_t st) {
   const Launch l = plan(s, n, [](const DevDesc& h) { return h.arm_nwg; });
   TimeScope ts(bwd ? TK_ARM : TK_NONE, st);
-  if (s[0]->precision == CC_BF16_FUSED && cc_arm_fused_supported(s[0]->lo.h))
-    return cc_launch_arm_fused(l, s[0]->lo.h, bwd, st);
+  if (s[0]->lo.h.arm_fused) return cc_launch_arm_fused(l, s[0]->lo.h, bwd, st);
   return cc_launch_arm_plain(l, s[0]->lo.h, bwd, st);
 }
 
@@ -674,6 +714,7 @@ int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, doub
   if (e == hipSuccess) e = cp(h.grad, zeros.data(), sizeof(float) * h.n_theta);
   if (e == hipSuccess) e = cp(h.arm_gtab, s->lo.arm_gtab.data(), sizeof(unsigned) * s->lo.arm_gtab.size());
   if (e == hipSuccess) e = cp(h.syn_gtab, s->lo.syn_gtab.data(), sizeof(unsigned) * s->lo.syn_gtab.size());
+  if (e == hipSuccess) e = cp(h.arm_ftab, s->lo.arm_ftab.data(), sizeof(unsigned) * s->lo.arm_ftab.size());
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete s;
@@ -821,9 +862,14 @@ int cc_debug_read(cc_state* s, const char* buffer, float* host, int64_t count, v
 }
 
 int cc_set_precision(cc_state* s, int precision) {
-  if (!s) return fail(CC_ESTATE, "state not initialised");
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
   if (precision != CC_FP32_PLAIN && precision != CC_BF16_FUSED) return fail(CC_EINVAL, "precision=%d", precision);
+  DevDesc& h = s->lo.h;
   s->precision = precision;
+  h.arm_fused = (precision == CC_BF16_FUSED && cc_arm_fused_supported(h)) ? 1 : 0;
+  h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
+  h.prod[h.prod_arm].nrows = h.arm_nwg;
+  HIPCHK(hipMemcpy(s->ddev, &h, sizeof(DevDesc), hipMemcpyHostToDevice));
   return CC_OK;
 }
 

@@ -54,6 +54,8 @@ struct DevDesc {
   float *U, *dU, *X, *dXa, *dXb, *wp;
   double* wp2;
   unsigned* arm_gtab;
+  unsigned* arm_ftab;           // fused ARM: parameter -> (grid, accumulator, row, column)
+  int arm_nwg_plain, arm_nwg_fused, arm_fused;  // arm_fused: planes A/B hold the rate gradient
   unsigned* syn_gtab;
   double *lp_bits, *lp_mse, *scal;
 };
@@ -110,3 +112,6 @@ int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
 #define CC_SYN_CPW 4
 #define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
+#define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
+
+int cc_arm_fused_supported(const DevDesc& h);

@@ -1,6 +1,500 @@
-// ARM entropy model, fused BF16 MFMA form (placeholder until the MFMA kernel
-// lands: reports the shape as unsupported so the plain kernel runs).
+// ARM entropy model, fused BF16 MFMA form (gfx950, v_mfma_f32_32x32x16_bf16).
+//
+// Same mathematics as the plain kernel (Section III-A: causal context,
+// inter-feature context, MLP with stabilizer, Laplace rate; and its
+// backward), with the three GEMM-shaped parts on the matrix cores:
+//   forward   H1 = relu(W1 C + b1), H2 = relu(W2 H1 + b2)
+//   backward  dH1 = W2^T dH2', dC = W1^T dH1'
+//   weights   dW1 = dH1' C^T, dW2 = dH2' H1^T, dW3/dWs/dW_ifce likewise
+// with latent positions on the N axis: 32 positions per MFMA, operands in
+// BF16, accumulation in FP32.  The output layer (2 units), the stabilizer,
+// the rate and its derivatives run in FP32 on the vector ALUs.
+//
+// Work: one workgroup (4 wavefronts) per band of 2 rows of one grid, swept in
+// segments of 128 columns; wavefront w owns columns [32 w, 32 w + 32) of the
+// segment in both rows.  The quantised latents of the band and its causal
+// halo (4 rows above, 4 columns each side) are staged in LDS.  The context
+// gradient is scattered into an LDS accumulator covering the band plus that
+// halo, in a fixed order (even wavefronts, then odd ones; within a
+// wavefront, lanes 0-31 then 32-63), so the result is deterministic; each
+// band writes its own rows to plane A and the 4 halo rows above it to planes
+// B1 and B2 (for the bands one and two above).  Weight gradients stay in MFMA accumulators across the
+// band and are reduced over the 8 wavefronts in a fixed order into one
+// partial row per workgroup.
 #include "cc_internal.h"
 
-int cc_arm_fused_supported(const DevDesc&) { return 0; }
-int cc_launch_arm_fused(const Launch&, const DevDesc&, int, hipStream_t) { return CC_EINVAL; }
+#include <math.h>
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr float INV_LN2 = 1.4426950408889634f;
+constexpr int TH = CC_FUSED_BAND;  // band height (rows)
+constexpr int HALO = 4;            // causal reach: rows above, columns each side
+constexpr int NW = 4;              // wavefronts per workgroup
+constexpr int SW = 32 * NW;        // segment width
+constexpr int WR = SW + 2 * HALO;  // LDS row: segment plus the halo columns
+
+__device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Row of the 32x32 output held by accumulator register i of a lane in half h.
+__device__ __forceinline__ int mrow(int i, int h) { return (i >> 2) * 8 + 4 * h + (i & 3); }
+// Hidden unit carried at K index k when the previous layer's output
+// registers are fed back as the B operand: k = 16 s + 8 h + i <-> register
+// 8 s + i of half h.
+__device__ __forceinline__ int kunit(int k) {
+  const int s = k >> 4, h = (k >> 3) & 1, i = k & 7;
+  return mrow(8 * s + i, h);
+}
+
+__device__ __forceinline__ void laplace_bits(float dd, float ib, float& bits, float& gd, float& gl) {
+  const float ad = fabsf(dd);
+  if (ad >= 0.5f) {
+    const float a = ad - 0.5f;
+    bits = a * ib * INV_LN2 - log2f(-0.5f * expm1f(-ib));
+    gd = copysignf(ib * INV_LN2, dd);
+    gl = (ib / expm1f(ib) - a * ib) * INV_LN2;
+  } else {
+    const float x1 = (0.5f + dd) * ib, x2 = (0.5f - dd) * ib;
+    const float e1 = expm1f(-x1), e2 = expm1f(-x2);
+    const float p = -0.5f * (e1 + e2);
+    bits = -log2f(p);
+    const float q = INV_LN2 / p;
+    gd = -0.5f * ib * (e1 - e2) * q;
+    gl = 0.5f * ((e1 + 1.0f) * x1 + (e2 + 1.0f) * x2) * q;
+  }
+}
+
+// Transposing tile: values written at [row][col], operands read as 8
+// consecutive columns of one row.
+struct Tile {
+  __bf16 v[32][32];
+};
+
+// Weight-gradient operands are split x = hi + lo (two BF16 numbers, about 16
+// significant bits together); a product is accumulated as
+// hi*hi + hi*lo + lo*hi, which keeps gradient sums with heavy cancellation
+// accurate to well below the BF16 rounding of one operand.
+struct TilePair {
+  Tile* hi;
+  Tile* lo;
+  __device__ __forceinline__ void put(int r, int c, float x) const {
+    const __bf16 h = (__bf16)x;
+    hi->v[r][c] = h;
+    lo->v[r][c] = (__bf16)(x - (float)h);
+  }
+};
+
+__device__ __forceinline__ f32x16 mfma_split(const TilePair& G, const TilePair& C, int n, int hh,
+                                             f32x16 acc) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    bf16x8 ah, al, bh, bl;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      ah[i] = G.hi->v[n][16 * s + 8 * hh + i];
+      al[i] = G.lo->v[n][16 * s + 8 * hh + i];
+      bh[i] = C.hi->v[n][16 * s + 8 * hh + i];
+      bl[i] = C.lo->v[n][16 * s + 8 * hh + i];
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int S, int F, int H1, int H2>
+__global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
+  constexpr int CTX = S + F;
+  static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 + CC_MAX_L - 1 <= 32, "shape");
+  __shared__ float ywin[HALO + TH][WR];
+  __shared__ float acc[HALO + TH][WR];
+  __shared__ Tile tg[NW], tc[NW], tgl[NW], tcl[NW];
+  __shared__ float wsum[3][32][33];
+  __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
+  __shared__ int soff[32];          // context slot -> LDS offset of its neighbour
+  __shared__ double bsh[NW];
+  __shared__ float carry[HALO + TH][2 * HALO];
+  __shared__ bf16x8 wop[4][2][64];
+
+  const int im = cc_find_img(Lc, blockIdx.x);
+  const DevDesc* d = Lc.d[im];
+  const int wg = blockIdx.x - Lc.tile0[im];
+  int k = 0, band = wg;
+  for (;;) {
+    const int nb = (d->gh[k] + TH - 1) / TH;
+    if (band < nb || k == d->L - 1) break;
+    band -= nb;
+    ++k;
+  }
+  const int h = d->gh[k], w = d->gw[k], nk = h * w;
+  const int y0 = band * TH;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, n = lane & 31, hh = lane >> 5;
+  const float* P = d->theta + d->n_lat;
+  const float* W1 = P + d->p_aw[0];
+  const float* W2 = P + d->p_aw[1];
+  const float* W3 = P + d->p_aw[2];
+  const bool stab = d->arm_stab != 0;
+  const bool has_ifce = F > 0 && k < d->G;
+  const int nin = d->L - k - 1;
+  const float rs = d->rate_scale;
+  const float* yg = d->yhat + d->goff[k];
+
+  // ---- per-workgroup constants
+  if (tid < 32) {
+    const int m = tid;
+    vec[0][m] = m < H1 ? P[d->p_ab[0] + m] : 0.0f;
+    vec[1][m] = m < H2 ? P[d->p_ab[1] + m] : 0.0f;
+    vec[2][m] = m < H2 ? W3[m] : 0.0f;
+    vec[3][m] = m < H2 ? W3[H2 + m] : 0.0f;
+    vec[4][m] = (stab && m < CTX) ? P[d->p_asw + m] : 0.0f;
+    vec[5][m] = (stab && m < CTX) ? P[d->p_asw + CTX + m] : 0.0f;
+    soff[m] = m < S ? d->dy[m] * WR + d->dx[m] : 0;
+  }
+  // A operands (weights, BF16) per lane and K step, kept in LDS: operand
+  // (matrix mat, step s) of lane l is wop[mat][s][l]
+  if (wave == 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 a1, a2, a2t, a1t;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int kk = 16 * s + 8 * hh + i, u = kunit(kk), m = n;
+        a1[i] = (__bf16)((m < H1 && kk < CTX) ? W1[m * CTX + kk] : 0.0f);
+        a2[i] = (__bf16)((m < H2 && u < H1) ? W2[m * H1 + u] : 0.0f);
+        a2t[i] = (__bf16)((m < H1 && u < H2) ? W2[u * H1 + m] : 0.0f);
+        a1t[i] = (__bf16)((m < CTX && u < H1) ? W1[u * CTX + m] : 0.0f);
+      }
+      wop[0][s][lane] = a1;
+      wop[1][s][lane] = a2;
+      wop[2][s][lane] = a2t;
+      wop[3][s][lane] = a1t;
+    }
+  }
+  const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
+  const float bs0 = stab ? P[d->p_asb] : 0.0f, bs1 = stab ? P[d->p_asb + 1] : 0.0f;
+  // IFCE weights for this grid (FP32, read through the scalar cache)
+  const float* Wi = has_ifce ? P + d->p_iw[k] : P;
+  const float* Bi = has_ifce ? P + d->p_ib[k] : P;
+
+  f32x16 acc1 = {}, acc2 = {}, acc3 = {};
+  double bsum = 0.0;
+  for (int i = tid; i < (HALO + TH) * WR; i += NW * 64) (&acc[0][0])[i] = 0.0f;
+
+  const int nseg = (w + SW - 1) / SW;
+  for (int seg = 0; seg < nseg; ++seg) {
+    const int x0 = seg * SW;
+    // stage latents: rows y0-4 .. y0+TH-1, columns x0-4 .. x0+SW+3 (zero outside)
+    for (int i = tid; i < (HALO + TH) * WR; i += NW * 64) {
+      const int r = i / WR, c = i - r * WR;
+      const int gy = y0 - HALO + r, gx = x0 - HALO + c;
+      (&ywin[0][0])[i] = (gy >= 0 && gy < h && gx >= 0 && gx < w) ? yg[gy * w + gx] : 0.0f;
+    }
+    __syncthreads();
+
+    for (int r = 0; r < TH; ++r) {
+      const int y = y0 + r, x = x0 + 32 * wave + n;
+      const bool valid = y < h && x < w;
+      const int lc = HALO + 32 * wave + n;       // LDS column of this position
+      // ---- context (FP32) in operand order: slot kk = 16 s + 8 hh + i
+      float cf[2][8];
+      float r_in[CC_MAX_L - 1];
+#pragma unroll
+      for (int q = 0; q < CC_MAX_L - 1; ++q) r_in[q] = 0.0f;
+      if (has_ifce && valid) {
+#pragma unroll
+        for (int q = 0; q < CC_MAX_L - 1; ++q)
+          if (q < nin) {
+            const int j = k + 1 + q;
+            r_in[q] = d->yhat[d->goff[j] + (y >> (q + 1)) * d->gw[j] + (x >> (q + 1))];
+          }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int kk = 16 * s + 8 * hh + i;
+          float v = 0.0f;
+          if (kk < S) {
+            v = (&ywin[HALO + r][lc])[soff[kk]];
+          } else if (kk < CTX && has_ifce) {
+            const int f = kk - S;
+            float a = Bi[f];
+#pragma unroll
+            for (int q = 0; q < CC_MAX_L - 1; ++q)
+              if (q < nin) a += Wi[f * nin + q] * r_in[q];
+            v = a;
+          }
+          cf[s][i] = v;
+        }
+      bf16x8 bc[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bc[s][i] = (__bf16)cf[s][i];
+      // ---- layer 1 and 2
+      f32x16 z = {};
+      f32x16 D1 = mfma(wop[0][0][lane], bc[0], z);
+      if (CTX > 16) D1 = mfma(wop[0][1][lane], bc[1], D1);
+      float h1[16], h2[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) h1[i] = fmaxf(D1[i] + vec[0][mrow(i, hh)], 0.0f);
+      bf16x8 bh[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bh[s][i] = (__bf16)h1[8 * s + i];
+      f32x16 D2 = mfma(wop[1][0][lane], bh[0], z);
+      D2 = mfma(wop[1][1][lane], bh[1], D2);
+      float o0 = 0.0f, o1 = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        h2[i] = fmaxf(D2[i] + vec[1][mrow(i, hh)], 0.0f);
+        o0 += vec[2][mrow(i, hh)] * h2[i];
+        o1 += vec[3][mrow(i, hh)] * h2[i];
+      }
+      if (stab) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int kk = 16 * s + 8 * hh + i;
+            o0 += vec[4][kk] * cf[s][i];
+            o1 += vec[5][kk] * cf[s][i];
+          }
+      }
+      const float p0 = __shfl_xor(o0, 32), p1 = __shfl_xor(o1, 32);
+      const float mu = (o0 + p0) + (b30 + bs0);
+      const float ls = (o1 + p1) + (b31 + bs1);
+      // ---- rate (FP32)
+      const float lcl = fminf(fmaxf(ls, d->lmin), d->lmax);
+      const bool lin = ls >= d->lmin && ls <= d->lmax;
+      const float yv = ywin[HALO + r][lc];
+      float bits, gd, gl;
+      laplace_bits(yv - mu, expf(-lcl), bits, gd, gl);
+      if (!(bits <= d->bits_max)) {
+        bits = d->bits_max;
+        gd = 0.0f;
+        gl = 0.0f;
+      }
+      if (!lin) gl = 0.0f;
+      if (!valid) {
+        bits = 0.0f;
+        gd = 0.0f;
+        gl = 0.0f;
+      }
+      if (hh == 0) bsum += (double)bits;
+      if (bwd <= 0) continue;
+
+      // ---- backward
+      const float dmu = -gd * rs, dl = gl * rs;
+      float dh2[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        dh2[i] = h2[i] > 0.0f ? vec[2][mrow(i, hh)] * dmu + vec[3][mrow(i, hh)] * dl : 0.0f;
+      bf16x8 bd[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bd[s][i] = (__bf16)dh2[8 * s + i];
+      f32x16 G1 = mfma(wop[2][0][lane], bd[0], z);
+      G1 = mfma(wop[2][1][lane], bd[1], G1);
+      float dh1[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dh1[i] = h1[i] > 0.0f ? G1[i] : 0.0f;
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bd[s][i] = (__bf16)dh1[8 * s + i];
+      f32x16 DC = mfma(wop[3][0][lane], bd[0], z);
+      DC = mfma(wop[3][1][lane], bd[1], DC);
+      float dc[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int m = mrow(i, hh);
+        dc[i] = DC[i] + (vec[4][m] * dmu + vec[5][m] * dl);
+      }
+      // IFCE slots of the context gradient
+      if (has_ifce && valid) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int m = mrow(i, hh);
+          if (m >= S && m < CTX) d->df[d->dfoff[k][0] + (m - S) * nk + y * w + x] = dc[i];
+        }
+      }
+
+      // ---- weight gradients: transpose through LDS, accumulate on MFMA
+      const TilePair G{&tg[wave], &tgl[wave]};
+      const TilePair C{&tc[wave], &tcl[wave]};
+      // (1) rows [dH1' | dmu dl], columns [context | 1]
+#pragma unroll
+      for (int i = 0; i < 16; ++i) G.put(mrow(i, hh), n, dh1[i]);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) C.put(16 * s + 8 * hh + i, n, cf[s][i]);
+      if (hh == 0) {
+        G.put(H1, n, dmu);
+        G.put(H1 + 1, n, dl);
+        C.put(CTX, n, 1.0f);
+      }
+      __builtin_amdgcn_wave_barrier();
+      acc1 = mfma_split(G, C, n, hh, acc1);
+      __builtin_amdgcn_wave_barrier();
+      // (2) rows dH2', columns [H1 | 1]
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        G.put(mrow(i, hh), n, dh2[i]);
+        C.put(mrow(i, hh), n, h1[i]);
+      }
+      if (hh == 0) C.put(H1, n, 1.0f);
+      __builtin_amdgcn_wave_barrier();
+      acc2 = mfma_split(G, C, n, hh, acc2);
+      __builtin_amdgcn_wave_barrier();
+      // (3) rows [dmu dl | dF], columns [H2 | 1 | r]
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        G.put(mrow(i, hh), n, 0.0f);
+        C.put(mrow(i, hh), n, h2[i]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (hh == 0) {
+        G.put(0, n, dmu);
+        G.put(1, n, dl);
+        C.put(H2, n, 1.0f);
+#pragma unroll
+        for (int q = 0; q < CC_MAX_L - 1; ++q)
+          if (H2 + 1 + q < 32) C.put(H2 + 1 + q, n, r_in[q]);
+      }
+      if (has_ifce) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int m = mrow(i, hh);
+          if (m >= S && m < CTX) G.put(2 + m - S, n, valid ? dc[i] : 0.0f);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      acc3 = mfma_split(G, C, n, hh, acc3);
+      __builtin_amdgcn_wave_barrier();
+
+      // ---- scatter the context gradient (and the direct term) into acc
+      const int base = (HALO + r) * WR + lc;
+      for (int ph = 0; ph < 2; ++ph) {
+        __syncthreads();
+        if ((wave & 1) == ph && valid) {
+          for (int half = 0; half < 2; ++half) {
+            if (hh == half) {
+#pragma unroll
+              for (int i = 0; i < 16; ++i) {
+                const int m = mrow(i, hh);
+                if (m < S) atomicAdd(&acc[0][0] + base + soff[m], dc[i]);
+              }
+              if (half == 0) atomicAdd(&acc[0][0] + base, gd * rs);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- write the finished columns of this segment and carry the last
+    // 2*HALO columns into the next one.  Row rr of acc is grid row
+    // y0 - HALO + rr: rows >= HALO belong to this band (plane A), rows
+    // [HALO - TH, HALO) to the band above (plane B1), rows [0, HALO - TH) to
+    // the band two above (plane B2).
+    if (bwd > 0) {
+      const bool last = seg == nseg - 1;
+      const int ncol = last ? WR : SW;
+      for (int i = tid; i < (HALO + TH) * ncol; i += NW * 64) {
+        const int rr = i / ncol, c = i - rr * ncol;
+        const int gy = y0 - HALO + rr, gx = x0 - HALO + c;
+        if (gx < 0 || gx >= w || gy < 0 || gy >= h) continue;
+        const int plane = rr >= HALO ? 0 : (rr >= HALO - TH ? 1 : 2);
+        d->dc[(size_t)plane * d->n_lat + d->goff[k] + gy * w + gx] = acc[rr][c];
+      }
+      __syncthreads();
+      if (tid < (HALO + TH) * 2 * HALO)
+        carry[tid / (2 * HALO)][tid % (2 * HALO)] = acc[tid / (2 * HALO)][SW + tid % (2 * HALO)];
+      __syncthreads();
+      for (int i = tid; i < (HALO + TH) * WR; i += NW * 64) {
+        const int rr = i / WR, c = i - rr * WR;
+        (&acc[0][0])[i] = c < 2 * HALO ? carry[rr][c] : 0.0f;
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- bits of this workgroup
+  for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off);
+  if (lane == 0) bsh[wave] = bsum;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int q = 0; q < NW; ++q) s += bsh[q];
+    d->lp_bits[wg] = s;
+  }
+  if (bwd <= 0) return;
+
+  // ---- weight gradients: fixed-order sum over wavefronts, one partial row
+  for (int q = 0; q < NW; ++q) {
+    if (wave == q) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int m = mrow(i, hh);
+        if (q == 0) {
+          wsum[0][m][n] = acc1[i];
+          wsum[1][m][n] = acc2[i];
+          wsum[2][m][n] = acc3[i];
+        } else {
+          wsum[0][m][n] += acc1[i];
+          wsum[1][m][n] += acc2[i];
+          wsum[2][m][n] += acc3[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* out = d->wp + d->prod[d->prod_arm].off + (size_t)wg * d->n_arm_par;
+  for (int p = tid; p < d->n_arm_par; p += NW * 64) {
+    const unsigned e = d->arm_ftab[p];
+    const int kr = (e >> 16) & 0xFF;
+    const int a = (e >> 10) & 3, row = (e >> 5) & 31, col = e & 31;
+    out[p] = (kr == 0xFF || kr == k) ? wsum[a][row][col] : 0.0f;
+  }
+}
+
+template <int S, int F, int H1, int H2>
+int launch_t(const Launch& l, int bwd, hipStream_t st) {
+  hipLaunchKernelGGL((k_arm_fused<S, F, H1, H2>), dim3(l.tile0[l.n]), dim3(NW * 64), 0, st, l, bwd);
+  return hipGetLastError() == hipSuccess ? CC_OK : CC_EDEVICE;
+}
+
+}  // namespace
+
+#define CC_FUSED_SHAPES(X) \
+  X(16, 0, 16, 16)         \
+  X(24, 6, 24, 24)         \
+  X(18, 6, 24, 24)         \
+  X(6, 2, 5, 4)            \
+  X(6, 2, 8, 8)            \
+  X(10, 4, 10, 10)         \
+  X(14, 6, 20, 20)
+
+int cc_arm_fused_supported(const DevDesc& h) {
+#define X(a, b, c, e) if (h.S == a && h.F == b && h.H1 == c && h.H2 == e) return 1;
+  CC_FUSED_SHAPES(X)
+#undef X
+  return 0;
+}
+
+int cc_launch_arm_fused(const Launch& l, const DevDesc& h, int bwd, hipStream_t st) {
+#define X(a, b, c, e) \
+  if (h.S == a && h.F == b && h.H1 == c && h.H2 == e) return launch_t<a, b, c, e>(l, bwd, st);
+  CC_FUSED_SHAPES(X)
+#undef X
+  return CC_EINVAL;
+}

@@ -141,11 +141,21 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L) {
   const int k = grid_of(d, i);
   const int h = d->gh[k], w = d->gw[k], li = i - d->goff[k];
   const int y = li / w, x = li - y * w;
-  float g = d->dyd[i];
-  const float* dc = d->dc + d->goff[k];
-  for (int m = 0; m < d->S; ++m) {
-    const int sy = y - d->dy[m], sx = x - d->dx[m];
-    if (sy >= 0 && sy < h && sx >= 0 && sx < w) g += dc[(size_t)m * d->n_lat + sy * w + sx];
+  float g;
+  if (d->arm_fused) {
+    // planes of the band-tiled kernel: own band, then the halo rows written
+    // by the bands one and two below (the causal reach is 4 rows)
+    g = d->dc[i];
+    const int band = y / CC_FUSED_BAND, nb = (h + CC_FUSED_BAND - 1) / CC_FUSED_BAND;
+    if (band + 1 < nb) g += d->dc[(size_t)d->n_lat + i];
+    if (band + 2 < nb) g += d->dc[(size_t)2 * d->n_lat + i];
+  } else {
+    g = d->dyd[i];
+    const float* dc = d->dc + d->goff[k];
+    for (int m = 0; m < d->S; ++m) {
+      const int sy = y - d->dy[m], sx = x - d->dx[m];
+      if (sy >= 0 && sy < h && sx >= 0 && sx < w) g += dc[(size_t)m * d->n_lat + sy * w + sx];
+    }
   }
   const float* P = d->theta + d->n_lat;
   const int nk = h * w;
