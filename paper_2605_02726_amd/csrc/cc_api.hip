@@ -203,7 +203,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   wpo += (long long)std::max(h.arm_nwg_plain, h.arm_nwg_fused) * h.n_arm_par;
   h.prod_ups1 = q;
   for (int j = 1; j < h.L; ++j) {
-    const int rows = cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE);
+    const int rows = cdiv(h.gh[j], CC_UPS_TILE) * cdiv(h.gw[j], CC_UPS_TILE);
     h.prod[q++] = {h.p_ups[j], 4, rows, 0, wpo};
     wpo += (long long)rows * 4;
   }
@@ -211,9 +211,10 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.prod[q++] = {h.p_sw[0], syn_end - h.p_sw[0], h.syn_nwg, 0, wpo};
   wpo += (long long)h.syn_nwg * (syn_end - h.p_sw[0]);
   h.prod_res0 = q;
+  h.res_nwg = cdiv(npix, CC_PIX_TILE * CC_RES_PPT);
   for (int r = 0; r < h.n_res; ++r) {
-    h.prod[q++] = {h.p_rw[r], 84, h.pix_ntile, 0, wpo};
-    wpo += (long long)h.pix_ntile * 84;
+    h.prod[q++] = {h.p_rw[r], 84, h.res_nwg, 0, wpo};
+    wpo += (long long)h.res_nwg * 84;
   }
   h.nprod = q;
   h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
@@ -574,7 +575,7 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
   }
   RET(forward_dist(s, n, 1, st));
   if (backward) {
-    const Launch lp = plan(s, n, [](const DevDesc& h) { return h.pix_ntile; });
+    const Launch lp = plan(s, n, [](const DevDesc& h) { return h.res_nwg; });
     int src_b = 0;
     for (int r = h0.n_res - 1; r >= 0; --r) {
       RET(cc_launch_res_bwd2(lp, r, src_b, st));
@@ -587,7 +588,9 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
     {
       TimeScope ts(TK_UPS_BWD, st);
       for (int j = 1; j < h0.L; ++j) {
-        const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE); });
+        const Launch l = plan(s, n, [j](const DevDesc& h) {
+          return cdiv(h.gh[j], CC_UPS_TILE) * cdiv(h.gw[j], CC_UPS_TILE);
+        });
         RET(cc_launch_ups_bwd(l, j, st));
       }
     }

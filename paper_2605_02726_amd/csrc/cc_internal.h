@@ -46,7 +46,7 @@ struct DevDesc {
   int mode, upd;
   // ---- producer geometry
   int arm_nchunk, arm_nwg, syn_nchunk, syn_nwg, pix_nwg, nprod;
-  int lat_ntile, pix_ntile;
+  int lat_ntile, pix_ntile, res_nwg;
   ProdSeg prod[CC_MAX_PROD];
   int prod_arm, prod_syn, prod_res0, prod_ups1;   // producer indices
   // ---- buffers (device pointers inside the slab)
@@ -59,6 +59,14 @@ struct DevDesc {
   unsigned* syn_gtab;
   double *lp_bits, *lp_mse, *scal;
 };
+
+// Read-only views used inside kernels: the descriptor and the decoder
+// parameters never change during a kernel that reads them (only the Adam and
+// set-step kernels write them, through plain pointers), so they are read in
+// the constant address space, which lets uniform reads go through scalar
+// loads (and weights feed FMAs as scalar operands).
+typedef __attribute__((address_space(4))) const struct DevDesc CDesc;
+typedef __attribute__((address_space(4))) const float CF;
 
 // Kernel argument describing one batched launch: blockIdx.x in
 // [tile0[i], tile0[i+1]) belongs to image i.
@@ -113,5 +121,7 @@ int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
 #define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
 #define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
+#define CC_UPS_TILE 16      // upsampling adjoint: input tile side
+#define CC_RES_PPT 8        // residual-layer adjoint: pixels per thread
 
 int cc_arm_fused_supported(const DevDesc& h);

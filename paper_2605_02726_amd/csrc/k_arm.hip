@@ -58,10 +58,10 @@ __global__ __launch_bounds__(64) void k_arm_plain(Launch Lc) {
   __shared__ float lds[BWD ? 64 * AST : 1];
 
   const int im = cc_find_img(Lc, blockIdx.x);
-  const DevDesc* d = Lc.d[im];
+  const CDesc* d = (const CDesc*)Lc.d[im];
   const int wg = blockIdx.x - Lc.tile0[im];
   const int lane = threadIdx.x;
-  const float* P0 = d->theta + d->n_lat;
+  const CF* P0 = (const CF*)(d->theta + d->n_lat);
   const bool stab = d->arm_stab != 0;
   const float rs = d->rate_scale;
 
@@ -76,16 +76,16 @@ __global__ __launch_bounds__(64) void k_arm_plain(Launch Lc) {
     // The weights are re-read (scalar loads) in every chunk: laundering the
     // base pointer keeps the compiler from hoisting ~1.5k loop-invariant
     // weights into vector registers.
-    const float* P = P0;
+    const CF* P = P0;
     asm volatile("" : "+s"(P));
-    const float* W1 = P + d->p_aw[0];
-    const float* B1 = P + d->p_ab[0];
-    const float* W2 = P + d->p_aw[1];
-    const float* B2 = P + d->p_ab[1];
-    const float* W3 = P + d->p_aw[2];
-    const float* B3 = P + d->p_ab[2];
-    const float* Ws = P + d->p_asw;
-    const float* Bs = P + d->p_asb;
+    const CF* W1 = P + d->p_aw[0];
+    const CF* B1 = P + d->p_ab[0];
+    const CF* W2 = P + d->p_aw[1];
+    const CF* B2 = P + d->p_ab[1];
+    const CF* W3 = P + d->p_aw[2];
+    const CF* B3 = P + d->p_ab[2];
+    const CF* Ws = P + d->p_asw;
+    const CF* Bs = P + d->p_asb;
     int k = 0, c0 = ch;
     for (;;) {
       const int nck = (d->gh[k] * d->gw[k] + 63) >> 6;
@@ -121,8 +121,8 @@ __global__ __launch_bounds__(64) void k_arm_plain(Launch Lc) {
             r[q] = d->yhat[d->goff[j] + (y >> (q + 1)) * d->gw[j] + (x >> (q + 1))];
           }
         }
-        const float* Wi = P + d->p_iw[k];
-        const float* Bi = P + d->p_ib[k];
+        const CF* Wi = P + d->p_iw[k];
+        const CF* Bi = P + d->p_ib[k];
 #pragma unroll
         for (int f = 0; f < F; ++f) {
           float s = Bi[f];

@@ -75,35 +75,19 @@ struct Tile {
   __bf16 v[32][32];
 };
 
-// Weight-gradient operands are split x = hi + lo (two BF16 numbers, about 16
-// significant bits together); a product is accumulated as
-// hi*hi + hi*lo + lo*hi, which keeps gradient sums with heavy cancellation
-// accurate to well below the BF16 rounding of one operand.
-struct TilePair {
-  Tile* hi;
-  Tile* lo;
-  __device__ __forceinline__ void put(int r, int c, float x) const {
-    const __bf16 h = (__bf16)x;
-    hi->v[r][c] = h;
-    lo->v[r][c] = (__bf16)(x - (float)h);
-  }
-};
-
-__device__ __forceinline__ f32x16 mfma_split(const TilePair& G, const TilePair& C, int n, int hh,
+// acc += G * C^T over the 32 positions of a chunk: A operand = 8
+// consecutive positions of row n of G, B operand = the same of row n of C.
+__device__ __forceinline__ f32x16 mfma_tiles(const Tile& G, const Tile& C, int n, int hh,
                                              f32x16 acc) {
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    bf16x8 ah, al, bh, bl;
+    bf16x8 a, b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      ah[i] = G.hi->v[n][16 * s + 8 * hh + i];
-      al[i] = G.lo->v[n][16 * s + 8 * hh + i];
-      bh[i] = C.hi->v[n][16 * s + 8 * hh + i];
-      bl[i] = C.lo->v[n][16 * s + 8 * hh + i];
+      a[i] = G.v[n][16 * s + 8 * hh + i];
+      b[i] = C.v[n][16 * s + 8 * hh + i];
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
   return acc;
 }
@@ -114,7 +98,8 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 + CC_MAX_L - 1 <= 32, "shape");
   __shared__ float ywin[HALO + TH][WR];
   __shared__ float acc[HALO + TH][WR];
-  __shared__ Tile tg[NW], tc[NW], tgl[NW], tcl[NW];
+  __shared__ Tile tg[3][NW], tc[3][NW];
+  __shared__ float pwin[CC_MAX_L - 1][SW / 2 + 1];   // IFCE parents of the segment
   __shared__ float wsum[3][32][33];
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
   __shared__ int soff[32];          // context slot -> LDS offset of its neighbour
@@ -123,7 +108,7 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   __shared__ bf16x8 wop[4][2][64];
 
   const int im = cc_find_img(Lc, blockIdx.x);
-  const DevDesc* d = Lc.d[im];
+  const CDesc* d = (const CDesc*)Lc.d[im];
   const int wg = blockIdx.x - Lc.tile0[im];
   int k = 0, band = wg;
   for (;;) {
@@ -135,10 +120,10 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   const int h = d->gh[k], w = d->gw[k], nk = h * w;
   const int y0 = band * TH;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, n = lane & 31, hh = lane >> 5;
-  const float* P = d->theta + d->n_lat;
-  const float* W1 = P + d->p_aw[0];
-  const float* W2 = P + d->p_aw[1];
-  const float* W3 = P + d->p_aw[2];
+  const CF* P = (const CF*)(d->theta + d->n_lat);
+  const CF* W1 = P + d->p_aw[0];
+  const CF* W2 = P + d->p_aw[1];
+  const CF* W3 = P + d->p_aw[2];
   const bool stab = d->arm_stab != 0;
   const bool has_ifce = F > 0 && k < d->G;
   const int nin = d->L - k - 1;
@@ -179,8 +164,8 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
   const float bs0 = stab ? P[d->p_asb] : 0.0f, bs1 = stab ? P[d->p_asb + 1] : 0.0f;
   // IFCE weights for this grid (FP32, read through the scalar cache)
-  const float* Wi = has_ifce ? P + d->p_iw[k] : P;
-  const float* Bi = has_ifce ? P + d->p_ib[k] : P;
+  const CF* Wi = has_ifce ? P + d->p_iw[k] : P;
+  const CF* Bi = has_ifce ? P + d->p_ib[k] : P;
 
   f32x16 acc1 = {}, acc2 = {}, acc3 = {};
   double bsum = 0.0;
@@ -195,25 +180,35 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
       const int gy = y0 - HALO + r, gx = x0 - HALO + c;
       (&ywin[0][0])[i] = (gy >= 0 && gy < h && gx >= 0 && gx < w) ? yg[gy * w + gx] : 0.0f;
     }
+    // parents of the band (y0 is even: both rows share each coarser row)
+    if (has_ifce) {
+      for (int i = tid; i < (CC_MAX_L - 1) * (SW / 2 + 1); i += NW * 64) {
+        const int q = i / (SW / 2 + 1), c = i - q * (SW / 2 + 1);
+        if (q < nin) {
+          const int j = k + 1 + q;
+          const int py = y0 >> (q + 1), px = (x0 >> (q + 1)) + c;
+          pwin[q][c] = (py < d->gh[j] && px < d->gw[j]) ? d->yhat[d->goff[j] + py * d->gw[j] + px] : 0.0f;
+        }
+      }
+    }
     __syncthreads();
 
     for (int r = 0; r < TH; ++r) {
       const int y = y0 + r, x = x0 + 32 * wave + n;
       const bool valid = y < h && x < w;
       const int lc = HALO + 32 * wave + n;       // LDS column of this position
+      Tile& G1 = tg[0][wave];
+      Tile& G2 = tg[1][wave];
+      Tile& G3 = tg[2][wave];
+      Tile& C1 = tc[0][wave];
+      Tile& C2 = tc[1][wave];
+      Tile& C3 = tc[2][wave];
       // ---- context (FP32) in operand order: slot kk = 16 s + 8 hh + i
-      float cf[2][8];
       float r_in[CC_MAX_L - 1];
 #pragma unroll
-      for (int q = 0; q < CC_MAX_L - 1; ++q) r_in[q] = 0.0f;
-      if (has_ifce && valid) {
-#pragma unroll
-        for (int q = 0; q < CC_MAX_L - 1; ++q)
-          if (q < nin) {
-            const int j = k + 1 + q;
-            r_in[q] = d->yhat[d->goff[j] + (y >> (q + 1)) * d->gw[j] + (x >> (q + 1))];
-          }
-      }
+      for (int q = 0; q < CC_MAX_L - 1; ++q)
+        r_in[q] = (has_ifce && q < nin) ? pwin[q][(x >> (q + 1)) - (x0 >> (q + 1))] : 0.0f;
+      float cf[2][8];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -237,27 +232,17 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
       for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int i = 0; i < 8; ++i) bc[s][i] = (__bf16)cf[s][i];
-      // ---- layer 1 and 2
-      f32x16 z = {};
-      f32x16 D1 = mfma(wop[0][0][lane], bc[0], z);
-      if (CTX > 16) D1 = mfma(wop[0][1][lane], bc[1], D1);
-      float h1[16], h2[16];
+      const bool do_bwd = bwd > 0;
+      if (do_bwd) {
+        // weight-gradient columns known after the context: [context | 1]
 #pragma unroll
-      for (int i = 0; i < 16; ++i) h1[i] = fmaxf(D1[i] + vec[0][mrow(i, hh)], 0.0f);
-      bf16x8 bh[2];
+        for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) bh[s][i] = (__bf16)h1[8 * s + i];
-      f32x16 D2 = mfma(wop[1][0][lane], bh[0], z);
-      D2 = mfma(wop[1][1][lane], bh[1], D2);
-      float o0 = 0.0f, o1 = 0.0f;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        h2[i] = fmaxf(D2[i] + vec[1][mrow(i, hh)], 0.0f);
-        o0 += vec[2][mrow(i, hh)] * h2[i];
-        o1 += vec[3][mrow(i, hh)] * h2[i];
+          for (int i = 0; i < 8; ++i) C1.v[16 * s + 8 * hh + i][n] = bc[s][i];
+        if (hh == 0) C1.v[CTX][n] = (__bf16)1.0f;
       }
+      // stabilizer (FP32) while the context is live
+      float o0 = 0.0f, o1 = 0.0f;
       if (stab) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
@@ -267,6 +252,39 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
             o0 += vec[4][kk] * cf[s][i];
             o1 += vec[5][kk] * cf[s][i];
           }
+      }
+      // ---- layer 1 and 2
+      f32x16 z = {};
+      f32x16 D = mfma(wop[0][0][lane], bc[0], z);
+      if (CTX > 16) D = mfma(wop[0][1][lane], bc[1], D);
+      unsigned m1 = 0, m2 = 0;
+      bf16x8 bh[2];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float v = fmaxf(D[i] + vec[0][mrow(i, hh)], 0.0f);
+        m1 |= (v > 0.0f ? 1u : 0u) << i;
+        bh[i >> 3][i & 7] = (__bf16)v;
+      }
+      if (do_bwd) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) C2.v[mrow(i, hh)][n] = bh[i >> 3][i & 7];
+        if (hh == 0) C2.v[H1][n] = (__bf16)1.0f;
+      }
+      D = mfma(wop[1][0][lane], bh[0], z);
+      D = mfma(wop[1][1][lane], bh[1], D);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float v = fmaxf(D[i] + vec[1][mrow(i, hh)], 0.0f);
+        m2 |= (v > 0.0f ? 1u : 0u) << i;
+        o0 += vec[2][mrow(i, hh)] * v;
+        o1 += vec[3][mrow(i, hh)] * v;
+        if (do_bwd) C3.v[mrow(i, hh)][n] = (__bf16)v;
+      }
+      if (do_bwd && hh == 0) {
+        C3.v[H2][n] = (__bf16)1.0f;
+#pragma unroll
+        for (int q = 0; q < CC_MAX_L - 1; ++q)
+          if (H2 + 1 + q < 32) C3.v[H2 + 1 + q][n] = (__bf16)r_in[q];
       }
       const float p0 = __shfl_xor(o0, 32), p1 = __shfl_xor(o1, 32);
       const float mu = (o0 + p0) + (b30 + bs0);
@@ -289,97 +307,58 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
         gl = 0.0f;
       }
       if (hh == 0) bsum += (double)bits;
-      if (bwd <= 0) continue;
+      if (!do_bwd) continue;
 
       // ---- backward
       const float dmu = -gd * rs, dl = gl * rs;
-      float dh2[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-        dh2[i] = h2[i] > 0.0f ? vec[2][mrow(i, hh)] * dmu + vec[3][mrow(i, hh)] * dl : 0.0f;
       bf16x8 bd[2];
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < 16; ++i) {
+        const float v = ((m2 >> i) & 1u) ? vec[2][mrow(i, hh)] * dmu + vec[3][mrow(i, hh)] * dl : 0.0f;
+        bd[i >> 3][i & 7] = (__bf16)v;
+        G2.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
+      }
+      D = mfma(wop[2][0][lane], bd[0], z);
+      D = mfma(wop[2][1][lane], bd[1], D);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) bd[s][i] = (__bf16)dh2[8 * s + i];
-      f32x16 G1 = mfma(wop[2][0][lane], bd[0], z);
-      G1 = mfma(wop[2][1][lane], bd[1], G1);
-      float dh1[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) dh1[i] = h1[i] > 0.0f ? G1[i] : 0.0f;
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) bd[s][i] = (__bf16)dh1[8 * s + i];
-      f32x16 DC = mfma(wop[3][0][lane], bd[0], z);
-      DC = mfma(wop[3][1][lane], bd[1], DC);
+      for (int i = 0; i < 16; ++i) {
+        const float v = ((m1 >> i) & 1u) ? D[i] : 0.0f;
+        bd[i >> 3][i & 7] = (__bf16)v;
+        G1.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
+      }
+      if (hh == 0) {
+        G1.v[H1][n] = (__bf16)dmu;
+        G1.v[H1 + 1][n] = (__bf16)dl;
+      }
+      D = mfma(wop[3][0][lane], bd[0], z);
+      D = mfma(wop[3][1][lane], bd[1], D);
       float dc[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int m = mrow(i, hh);
-        dc[i] = DC[i] + (vec[4][m] * dmu + vec[5][m] * dl);
-      }
-      // IFCE slots of the context gradient
-      if (has_ifce && valid) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int m = mrow(i, hh);
-          if (m >= S && m < CTX) d->df[d->dfoff[k][0] + (m - S) * nk + y * w + x] = dc[i];
-        }
-      }
-
-      // ---- weight gradients: transpose through LDS, accumulate on MFMA
-      const TilePair G{&tg[wave], &tgl[wave]};
-      const TilePair C{&tc[wave], &tcl[wave]};
-      // (1) rows [dH1' | dmu dl], columns [context | 1]
-#pragma unroll
-      for (int i = 0; i < 16; ++i) G.put(mrow(i, hh), n, dh1[i]);
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) C.put(16 * s + 8 * hh + i, n, cf[s][i]);
-      if (hh == 0) {
-        G.put(H1, n, dmu);
-        G.put(H1 + 1, n, dl);
-        C.put(CTX, n, 1.0f);
-      }
-      __builtin_amdgcn_wave_barrier();
-      acc1 = mfma_split(G, C, n, hh, acc1);
-      __builtin_amdgcn_wave_barrier();
-      // (2) rows dH2', columns [H1 | 1]
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        G.put(mrow(i, hh), n, dh2[i]);
-        C.put(mrow(i, hh), n, h1[i]);
-      }
-      if (hh == 0) C.put(H1, n, 1.0f);
-      __builtin_amdgcn_wave_barrier();
-      acc2 = mfma_split(G, C, n, hh, acc2);
-      __builtin_amdgcn_wave_barrier();
-      // (3) rows [dmu dl | dF], columns [H2 | 1 | r]
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        G.put(mrow(i, hh), n, 0.0f);
-        C.put(mrow(i, hh), n, h2[i]);
+        dc[i] = D[i] + (vec[4][m] * dmu + vec[5][m] * dl);
+        G3.v[m][n] = (__bf16)0.0f;
       }
       __builtin_amdgcn_wave_barrier();
       if (hh == 0) {
-        G.put(0, n, dmu);
-        G.put(1, n, dl);
-        C.put(H2, n, 1.0f);
-#pragma unroll
-        for (int q = 0; q < CC_MAX_L - 1; ++q)
-          if (H2 + 1 + q < 32) C.put(H2 + 1 + q, n, r_in[q]);
+        G3.v[0][n] = (__bf16)dmu;
+        G3.v[1][n] = (__bf16)dl;
       }
       if (has_ifce) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int m = mrow(i, hh);
-          if (m >= S && m < CTX) G.put(2 + m - S, n, valid ? dc[i] : 0.0f);
+          if (m >= S && m < CTX) {
+            G3.v[2 + m - S][n] = (__bf16)(valid ? dc[i] : 0.0f);
+            if (valid) d->df[d->dfoff[k][0] + (m - S) * nk + y * w + x] = dc[i];
+          }
         }
       }
       __builtin_amdgcn_wave_barrier();
-      acc3 = mfma_split(G, C, n, hh, acc3);
+      // ---- weight gradients: three independent accumulations
+      acc1 = mfma_tiles(G1, C1, n, hh, acc1);
+      acc2 = mfma_tiles(G2, C2, n, hh, acc2);
+      acc3 = mfma_tiles(G3, C3, n, hh, acc3);
       __builtin_amdgcn_wave_barrier();
 
       // ---- scatter the context gradient (and the direct term) into acc

@@ -55,7 +55,7 @@ __device__ __forceinline__ float dsoftround(float x, float c, float invT) {
   return invT * c * (4.0f * e / (q * q));
 }
 
-__device__ __forceinline__ int grid_of(const DevDesc* d, int i) {
+__device__ __forceinline__ int grid_of(const CDesc* d, int i) {
   int k = 0;
   while (k + 1 < d->L && i >= d->goff[k + 1]) ++k;
   return k;
@@ -82,7 +82,7 @@ __global__ void k_set_step(StepLaunch s) {
 // d yhat / d y; or yhat = rint(y) with a straight-through derivative of 1.
 __global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L) {
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
   if (i >= d->n_lat) return;
   const float y = d->theta[i];
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L) {
 // grid c (at grid c+f) from level f-1 (at grid c+f-1), F channels.
 __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L, int f) {
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   int e = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
   for (int c = 0; c < d->G; ++c) {
     if (c + f > d->L - 1) continue;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L, int f) {
 // neighbour (reversed offsets) and the IFCE gradients of finer grids.
 __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L) {
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
   if (i >= d->n_lat) return;
   const int k = grid_of(d, i);
@@ -157,10 +157,10 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L) {
       if (sy >= 0 && sy < h && sx >= 0 && sx < w) g += dc[(size_t)m * d->n_lat + sy * w + sx];
     }
   }
-  const float* P = d->theta + d->n_lat;
+  const CF* P = (const CF*)(d->theta + d->n_lat);
   const int nk = h * w;
   for (int c = 0; c < d->G && c < k; ++c) {
-    const float* W = P + d->p_iw[c];          // [F, L-c-1]
+    const CF* W = P + d->p_iw[c];             // [F, L-c-1]
     const int q = k - c - 1, nin = d->L - c - 1;
     const float* D = d->df + d->dfoff[c][k - c];
     for (int f = 0; f < d->F; ++f) g += W[f * nin + q] * D[f * nk + li];
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L) {
 // untouched when frozen.
 __global__ __launch_bounds__(CC_ELT_TILE) void k_adam(Launch L) {
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
   if (i >= d->n_theta) return;
   if (i < d->n_lat && !d->upd) return;
@@ -199,7 +199,7 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
 // FP64 totals of one image in a fixed order: scal = (loss, bits, mse, finite).
 __global__ __launch_bounds__(256) void k_lreduce(Launch L) {
   __shared__ double sh[256];
-  const DevDesc* d = L.d[blockIdx.x];
+  const CDesc* d = (const CDesc*)L.d[blockIdx.x];
   double b = 0.0, m = 0.0;
   for (int r = threadIdx.x; r < d->arm_nwg; r += 256) b += d->lp_bits[r];
   const double bits = block_sum_256(b, sh);
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_lreduce(Launch L) {
 __global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
   __shared__ double sh[4][64];
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int b = blockIdx.x - L.tile0[im];
   const int pb = b / CC_WRED_SPLIT, s = b - pb * CC_WRED_SPLIT;
   const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
@@ -231,11 +231,11 @@ __global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
     int q = 0;
     while (q < d->nprod && !(p >= d->prod[q].pbeg && p < d->prod[q].pbeg + d->prod[q].pcnt)) ++q;
     if (q < d->nprod) {
-      const ProdSeg g = d->prod[q];
-      const int per = (g.nrows + CC_WRED_SPLIT - 1) / CC_WRED_SPLIT;
-      const int r0 = s * per, r1 = min(g.nrows, r0 + per);
-      const float* base = d->wp + g.off + (p - g.pbeg);
-      for (int r = r0 + sub; r < r1; r += 4) acc += (double)base[(size_t)r * g.pcnt];
+      const int nrows = d->prod[q].nrows, pcnt = d->prod[q].pcnt;
+      const int per = (nrows + CC_WRED_SPLIT - 1) / CC_WRED_SPLIT;
+      const int r0 = s * per, r1 = min(nrows, r0 + per);
+      const float* base = d->wp + d->prod[q].off + (p - d->prod[q].pbeg);
+      for (int r = r0 + sub; r < r1; r += 4) acc += (double)base[(size_t)r * pcnt];
     }
   }
   sh[sub][lane] = acc;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
 // Pass 2: gradient of decoder parameter p = sum of the row splits.
 __global__ __launch_bounds__(CC_ELT_TILE) void k_wreduce2(Launch L) {
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int p = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
   if (p >= d->n_par) return;
   double acc = 0.0;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_wreduce2(Launch L) {
 
 __global__ __launch_bounds__(CC_ELT_TILE) void k_copy_out(Launch L, float* out) {
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
   const int n = 3 * d->H * d->W;
   if (i >= n) return;

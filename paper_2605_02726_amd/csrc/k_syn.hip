@@ -30,7 +30,7 @@ __device__ __forceinline__ void out_taps(int o, int n, int* t, int* idx) {
 __device__ __forceinline__ float tapv(const float* h, int t) { return h[t < 4 ? t : 7 - t]; }
 
 // Input channel ch of T_j at position p (grid j).
-__device__ __forceinline__ const float* tchan(const DevDesc* d, int j, int ch) {
+__device__ __forceinline__ const float* tchan(const CDesc* d, int j, int ch) {
   return ch == 0 ? d->yhat + d->goff[j] : d->U + d->uoff[j + 1] + (size_t)(ch - 1) * d->gh[j] * d->gw[j];
 }
 
@@ -46,12 +46,13 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // U_j = Up_j(T_j): one thread per output pixel of grid j-1, all channels.
 __global__ __launch_bounds__(CC_PIX_TILE) void k_ups_fwd(Launch L, int j) {
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int ho = d->gh[j - 1], wo = d->gw[j - 1], hi = d->gh[j], wi = d->gw[j];
   const int p = (blockIdx.x - L.tile0[im]) * CC_PIX_TILE + threadIdx.x;
   if (p >= ho * wo) return;
   const int oy = p / wo, ox = p - oy * wo;
-  const float* h = d->theta + d->n_lat + d->p_ups[j];
+  const CF* hc = (const CF*)(d->theta + d->n_lat + d->p_ups[j]);
+  const float h[4] = {hc[0], hc[1], hc[2], hc[3]};
   int ty[4], iy[4], tx[4], ix[4];
   out_taps(oy, hi, ty, iy);
   out_taps(ox, wi, tx, ix);
@@ -89,89 +90,129 @@ __device__ __forceinline__ float axis_w(const float* h, int o, int i, int n) {
   return w;
 }
 
-// Adjoint of level j: dT_j = Up_j^T(dU_j), one thread per input pixel of
-// grid j, all channels; channel 0 is the distortion gradient of yhat^(j),
-// channels >= 1 are dU_{j+1}.  The same thread adds the tap gradient of its
-// 2x2 block of outputs; the workgroup writes one partial row of 4 values.
-__global__ __launch_bounds__(CC_PIX_TILE) void k_ups_bwd(Launch L, int j) {
-  __shared__ float sh[4][CC_PIX_TILE / 64];
+// Adjoint of level j on 16x16 tiles of grid j (inputs), all channels.
+// With R = column adjoint of dU_j (rows: outputs, columns: inputs) and
+// Bm = row adjoint (rows: inputs, columns: outputs), the input gradient is
+// the row adjoint of R, and the tap gradient of the symmetric kernel is
+//   sum over (output row oy, input column ix) of R[oy][ix] * d/dh of the row
+//   taps of oy applied to T, plus sum over (input row iy, output column ox)
+//   of Bm[iy][ox] * d/dh of the column taps of ox applied to T,
+// each (oy, ix) / (iy, ox) pair owned by exactly one tile (the tile of ix /
+// iy whose output rows / columns 2*tile .. 2*tile+31 contain oy / ox).
+// Channel 0 of dT_j is the distortion gradient of yhat^(j), channels >= 1 are
+// dU_{j+1}.  One partial row of 4 tap gradients per workgroup.
+constexpr int UT = CC_UPS_TILE;   // input tile side
+constexpr int UG = 2 * UT + 6;   // output window side (2*UT + 3 + 3)
+constexpr int UTW = UT + 4;      // input window side (2 each side)
+
+__global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
+  __shared__ float g[UG][UG + 1];
+  __shared__ float t[UTW][UTW + 1];
+  __shared__ float R[UG][UT + 1];
+  __shared__ float Bm[UT][2 * UT + 1];
+  __shared__ float wxs[UT][8], wys[UT][8];
+  __shared__ float sh[4][4];
   const int im = cc_find_img(L, blockIdx.x);
-  const DevDesc* d = L.d[im];
+  const CDesc* d = (const CDesc*)L.d[im];
   const int wgi = blockIdx.x - L.tile0[im];
   const int ho = d->gh[j - 1], wo = d->gw[j - 1], hi = d->gh[j], wi = d->gw[j];
-  const int p = wgi * CC_PIX_TILE + threadIdx.x;
-  const float* h = d->theta + d->n_lat + d->p_ups[j];
+  const int ntx = (wi + UT - 1) / UT;
+  const int iy0 = (wgi / ntx) * UT, ix0 = (wgi % ntx) * UT;
+  const CF* hp = (const CF*)(d->theta + d->n_lat + d->p_ups[j]);
+  const float hv[4] = {hp[0], hp[1], hp[2], hp[3]};
+  const int tid = threadIdx.x;
+  if (tid < UT * 8) {
+    const int a = tid & 7, q = tid >> 3;
+    const int iy = iy0 + q, ix = ix0 + q;
+    const int oy = 2 * iy - 3 + a, ox = 2 * ix - 3 + a;
+    wys[q][a] = (iy < hi && oy >= 0 && oy < ho) ? axis_w(hv, oy, iy, hi) : 0.0f;
+    wxs[q][a] = (ix < wi && ox >= 0 && ox < wo) ? axis_w(hv, ox, ix, wi) : 0.0f;
+  }
   const int nch = d->L - j;
-  const float* dU = d->dU + d->uoff[j];
   float dh[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  if (p < hi * wi) {
-    const int iy = p / wi, ix = p - iy * wi;
-    float wy[8], wx[8];
-    int oys[8], oxs[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      oys[a] = 2 * iy - 3 + a;
-      oxs[a] = 2 * ix - 3 + a;
-      wy[a] = (oys[a] >= 0 && oys[a] < ho) ? axis_w(h, oys[a], iy, hi) : 0.0f;
-      wx[a] = (oxs[a] >= 0 && oxs[a] < wo) ? axis_w(h, oxs[a], ix, wi) : 0.0f;
+  for (int ch = 0; ch < nch; ++ch) {
+    const float* gsrc = d->dU + d->uoff[j] + (size_t)ch * ho * wo;
+    const float* tsrc = tchan(d, j, ch);
+    __syncthreads();
+    for (int i = tid; i < UG * UG; i += 256) {
+      const int r = i / UG, c = i - r * UG;
+      const int oy = 2 * iy0 - 3 + r, ox = 2 * ix0 - 3 + c;
+      g[r][c] = (oy >= 0 && oy < ho && ox >= 0 && ox < wo) ? gsrc[oy * wo + ox] : 0.0f;
     }
-    for (int ch = 0; ch < nch; ++ch) {
-      const float* g = dU + (size_t)ch * ho * wo;
-      float s = 0.0f;
+    for (int i = tid; i < UTW * UTW; i += 256) {
+      const int r = i / UTW, c = i - r * UTW;
+      t[r][c] = tsrc[clampi(iy0 - 2 + r, 0, hi - 1) * wi + clampi(ix0 - 2 + c, 0, wi - 1)];
+    }
+    __syncthreads();
+    for (int i = tid; i < UG * UT; i += 256) {
+      const int r = i / UT, q = i - r * UT;
+      float a = 0.0f;
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        if (wy[a] == 0.0f) continue;
-        float r = 0.0f;
+      for (int b = 0; b < 8; ++b) a += wxs[q][b] * g[r][2 * q + b];
+      R[r][q] = a;
+    }
+    for (int i = tid; i < UT * 2 * UT; i += 256) {
+      const int q = i / (2 * UT), c = i - q * (2 * UT);
+      float a = 0.0f;
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
-          if (wx[b] != 0.0f) r += wx[b] * g[oys[a] * wo + oxs[b]];
-        s += wy[a] * r;
+      for (int b = 0; b < 8; ++b) a += wys[q][b] * g[2 * q + b][c + 3];
+      Bm[q][c] = a;
+    }
+    __syncthreads();
+    {
+      const int q = tid / UT, p = tid - q * UT;   // 256 = 16 x 16 inputs
+      const int iy = iy0 + q, ix = ix0 + p;
+      if (iy < hi && ix < wi) {
+        float a = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) a += wys[q][b] * R[2 * q + b][p];
+        if (ch == 0)
+          d->dyq[d->goff[j] + iy * wi + ix] = a;
+        else
+          d->dU[d->uoff[j + 1] + (size_t)(ch - 1) * hi * wi + iy * wi + ix] = a;
       }
-      if (ch == 0)
-        d->dyq[d->goff[j] + p] = s;
-      else
-        d->dU[d->uoff[j + 1] + (size_t)(ch - 1) * hi * wi + p] = s;
     }
-    // tap gradient over the outputs (2 iy + a, 2 ix + b), a, b in {0, 1}
+    // tap gradients: term over (oy owned, ix in tile) and (iy in tile, ox owned)
+    for (int i = tid; i < 2 * UT * UT; i += 256) {
+      const int ol = i / UT, p = i - ol * UT;      // output row offset, input column
+      const int oy = 2 * iy0 + ol, ix = ix0 + p;
+      if (oy < ho && ix < wi) {
+        int tt[4], idx[4];
+        out_taps(oy, hi, tt, idx);
+        const float rv = R[ol + 3][p];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+        for (int a = 0; a < 4; ++a) {
+          const float v = rv * t[idx[a] - (iy0 - 2)][p + 2];
+          const int qq = tt[a] < 4 ? tt[a] : 7 - tt[a];
+          dh[qq] += v;
+        }
+      }
+      const int q = i / (2 * UT), oc = i - q * (2 * UT);   // input row, output column offset
+      const int iy = iy0 + q, ox = 2 * ix0 + oc;
+      if (iy < hi && ox < wo) {
+        int tt[4], idx[4];
+        out_taps(ox, wi, tt, idx);
+        const float bv = Bm[q][oc];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int oy = 2 * iy + a, ox = 2 * ix + b;
-        int ty[4], yy[4], tx[4], xx[4];
-        out_taps(oy, hi, ty, yy);
-        out_taps(ox, wi, tx, xx);
-        for (int ch = 0; ch < nch; ++ch) {
-          const float* in = tchan(d, j, ch);
-          const float g = dU[(size_t)ch * ho * wo + oy * wo + ox];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const float tv = g * in[yy[u] * wi + xx[v]];
-              const int qy = ty[u] < 4 ? ty[u] : 7 - ty[u];
-              const int qx = tx[v] < 4 ? tx[v] : 7 - tx[v];
-              const float ux = tapv(h, tx[v]), uy = tapv(h, ty[u]);
-              dh[qy] += tv * ux;
-              dh[qx] += tv * uy;
-            }
-          }
+        for (int a = 0; a < 4; ++a) {
+          const float v = bv * t[q + 2][idx[a] - (ix0 - 2)];
+          const int qq = tt[a] < 4 ? tt[a] : 7 - tt[a];
+          dh[qq] += v;
         }
       }
     }
   }
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int wv = tid >> 6, ln = tid & 63;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float s = wave_sum(dh[q]);
-    if (ln == 0) sh[q][wv] = s;
+    const float s2 = wave_sum(dh[q]);
+    if (ln == 0) sh[q][wv] = s2;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
-    float s = 0.0f;
-    for (int w = 0; w < CC_PIX_TILE / 64; ++w) s += sh[threadIdx.x][w];
-    const ProdSeg& g = d->prod[d->prod_ups1 + j - 1];
-    d->wp[g.off + (size_t)wgi * 4 + threadIdx.x] = s;
+  if (tid < 4) {
+    const float s2 = (sh[tid][0] + sh[tid][1]) + (sh[tid][2] + sh[tid][3]);
+    const long long pg_off = d->prod[d->prod_ups1 + j - 1].off;
+    d->wp[pg_off + (size_t)wgi * 4 + tid] = s2;
   }
 }
 
@@ -183,11 +224,11 @@ struct SynShape {
 
 // Trunk of one pixel: z (L <= 8 values) -> hidden -> 3, plus stabilizer.
 template <int NH, int W1, int W2>
-__device__ __forceinline__ void syn_mlp(const DevDesc* d, const float* P, const float* z,
+__device__ __forceinline__ void syn_mlp(const CDesc* d, const CF* P, const float* z,
                                         float* h1, float* h2, float* out) {
   const int L = d->L;
-  const float* Wa = P + d->p_sw[0];
-  const float* Ba = P + d->p_sb[0];
+  const CF* Wa = P + d->p_sw[0];
+  const CF* Ba = P + d->p_sb[0];
 #pragma unroll
   for (int a = 0; a < W1; ++a) {
     float s = Ba[a];
@@ -197,8 +238,8 @@ __device__ __forceinline__ void syn_mlp(const DevDesc* d, const float* P, const 
     h1[a] = fmaxf(s, 0.0f);
   }
   if constexpr (NH == 2) {
-    const float* Wb = P + d->p_sw[1];
-    const float* Bb = P + d->p_sb[1];
+    const CF* Wb = P + d->p_sw[1];
+    const CF* Bb = P + d->p_sb[1];
 #pragma unroll
     for (int a = 0; a < W2; ++a) {
       float s = Bb[a];
@@ -209,8 +250,8 @@ __device__ __forceinline__ void syn_mlp(const DevDesc* d, const float* P, const 
   }
   constexpr int WL = SynShape<NH, W1, W2>::WL;
   const float* hl = NH == 2 ? h2 : h1;
-  const float* Wc = P + d->p_sw[NH];
-  const float* Bc = P + d->p_sb[NH];
+  const CF* Wc = P + d->p_sw[NH];
+  const CF* Bc = P + d->p_sb[NH];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     float s = Bc[c];
@@ -219,8 +260,8 @@ __device__ __forceinline__ void syn_mlp(const DevDesc* d, const float* P, const 
     out[c] = s;
   }
   if (d->syn_stab) {
-    const float* Ws = P + d->p_ssw;
-    const float* Bs = P + d->p_ssb;
+    const CF* Ws = P + d->p_ssw;
+    const CF* Bs = P + d->p_ssb;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float s = Bs[c];
@@ -232,7 +273,7 @@ __device__ __forceinline__ void syn_mlp(const DevDesc* d, const float* P, const 
   }
 }
 
-__device__ __forceinline__ void load_z(const DevDesc* d, int p, float* z) {
+__device__ __forceinline__ void load_z(const CDesc* d, int p, float* z) {
   const int n = d->H * d->W;
   z[0] = d->yhat[p];
 #pragma unroll
@@ -241,7 +282,7 @@ __device__ __forceinline__ void load_z(const DevDesc* d, int p, float* z) {
 
 // Squared error of one pixel, its gradient into dXa and the per-workgroup
 // FP64 partial sum.
-__device__ __forceinline__ void mse_epilogue(const DevDesc* d, int p, bool valid,
+__device__ __forceinline__ void mse_epilogue(const CDesc* d, int p, bool valid,
                                              const float* xo, int wgi, double* sh) {
   const int n = d->H * d->W;
   double sq = 0.0;
@@ -268,12 +309,12 @@ template <int NH, int W1, int W2>
 __global__ __launch_bounds__(CC_PIX_TILE) void k_syn_fwd(Launch Lc, int final_mse) {
   __shared__ double sh[CC_PIX_TILE / 64];
   const int im = cc_find_img(Lc, blockIdx.x);
-  const DevDesc* d = Lc.d[im];
+  const CDesc* d = (const CDesc*)Lc.d[im];
   const int wgi = blockIdx.x - Lc.tile0[im];
   const int n = d->H * d->W;
   const int p = wgi * CC_PIX_TILE + threadIdx.x;
   const bool valid = p < n;
-  const float* P = d->theta + d->n_lat;
+  const CF* P = (const CF*)(d->theta + d->n_lat);
   float z[CC_MAX_L], h1[W1], h2[NH == 2 ? W2 : 1], out[3];
   if (valid) {
     load_z(d, p, z);
@@ -298,11 +339,11 @@ __global__ __launch_bounds__(64) void k_syn_bwd(Launch Lc, int src_b) {
   constexpr int NQ = (PMAX + 63) / 64;
   __shared__ float lds[64 * AST];
   const int im = cc_find_img(Lc, blockIdx.x);
-  const DevDesc* d = Lc.d[im];
+  const CDesc* d = (const CDesc*)Lc.d[im];
   const int wg = blockIdx.x - Lc.tile0[im];
   const int lane = threadIdx.x;
   const int n = d->H * d->W, L = d->L;
-  const float* P0 = d->theta + d->n_lat;
+  const CF* P0 = (const CF*)(d->theta + d->n_lat);
   const float* G = src_b ? d->dXb : d->dXa;
   const int npar = d->prod[d->prod_syn].pcnt;
   float acc[NQ];
@@ -310,12 +351,12 @@ __global__ __launch_bounds__(64) void k_syn_bwd(Launch Lc, int src_b) {
   for (int q = 0; q < NQ; ++q) acc[q] = 0.0f;
   for (int ch = wg; ch < d->syn_nchunk; ch += d->syn_nwg) {
     // re-read the weights per chunk (see the ARM kernel)
-    const float* P = P0;
+    const CF* P = P0;
     asm volatile("" : "+s"(P));
-    const float* Wa = P + d->p_sw[0];
-    const float* Wb = P + d->p_sw[1];
-    const float* Wc = P + d->p_sw[NH];
-    const float* Ws = P + d->p_ssw;
+    const CF* Wa = P + d->p_sw[0];
+    const CF* Wb = P + d->p_sw[1];
+    const CF* Wc = P + d->p_sw[NH];
+    const CF* Ws = P + d->p_ssw;
     const int p = ch * 64 + lane;
     const bool valid = p < n;
     float z[CC_MAX_L], h1[W1], h2[NH == 2 ? W2 : 1], out[3];
@@ -392,8 +433,8 @@ __global__ __launch_bounds__(64) void k_syn_bwd(Launch Lc, int src_b) {
     }
     __syncthreads();
   }
-  const ProdSeg& g = d->prod[d->prod_syn];
-  float* out = d->wp + g.off + (size_t)wg * npar;
+  const long long g_off = d->prod[d->prod_syn].off;
+  float* out = d->wp + g_off + (size_t)wg * npar;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int p = lane + 64 * q;
@@ -407,13 +448,13 @@ __global__ __launch_bounds__(64) void k_syn_bwd(Launch Lc, int src_b) {
 __global__ __launch_bounds__(CC_PIX_TILE) void k_res_fwd(Launch Lc, int r, int last_mse) {
   __shared__ double sh[CC_PIX_TILE / 64];
   const int im = cc_find_img(Lc, blockIdx.x);
-  const DevDesc* d = Lc.d[im];
+  const CDesc* d = (const CDesc*)Lc.d[im];
   const int wgi = blockIdx.x - Lc.tile0[im];
   const int H = d->H, W = d->W, n = H * W;
   const int p = wgi * CC_PIX_TILE + threadIdx.x;
   const bool valid = p < n;
-  const float* Wr = d->theta + d->n_lat + d->p_rw[r];
-  const float* Br = d->theta + d->n_lat + d->p_rb[r];
+  const CF* Wr = (const CF*)(d->theta + d->n_lat + d->p_rw[r]);
+  const CF* Br = (const CF*)(d->theta + d->n_lat + d->p_rb[r]);
   const float* X = d->X + (size_t)r * 3 * n;
   float out[3] = {0.0f, 0.0f, 0.0f};
   if (valid) {
@@ -455,28 +496,28 @@ __device__ __forceinline__ int srcs(int q, int o, int n, int* ps) {
 
 // dX_r = dX_{r+1} + Conv3x3^T(dX_{r+1}) (adjoint of the replicate padding
 // included), plus the layer's weight gradient as one partial row of 84 per
-// workgroup.  src_b selects the input buffer; the output goes to the other.
+// workgroup; each thread handles RES_PPT pixels before the reduction.
+// src_b selects the input buffer; the output goes to the other.
 __global__ __launch_bounds__(CC_PIX_TILE) void k_res_bwd(Launch Lc, int r, int src_b) {
   __shared__ float sh[84][CC_PIX_TILE / 64];
   const int im = cc_find_img(Lc, blockIdx.x);
-  const DevDesc* d = Lc.d[im];
+  const CDesc* d = (const CDesc*)Lc.d[im];
   const int wgi = blockIdx.x - Lc.tile0[im];
   const int H = d->H, W = d->W, n = H * W;
-  const int p = wgi * CC_PIX_TILE + threadIdx.x;
-  const bool valid = p < n;
-  const float* Wr = d->theta + d->n_lat + d->p_rw[r];
+  const CF* Wr = (const CF*)(d->theta + d->n_lat + d->p_rw[r]);
   const float* G = src_b ? d->dXb : d->dXa;
   float* O = src_b ? d->dXa : d->dXb;
   const float* X = d->X + (size_t)r * 3 * n;
   float gw[84];
 #pragma unroll
   for (int q = 0; q < 84; ++q) gw[q] = 0.0f;
-  if (valid) {
+  for (int k = 0; k < CC_RES_PPT; ++k) {
+    const int p = (wgi * CC_RES_PPT + k) * CC_PIX_TILE + threadIdx.x;
+    if (p >= n) break;
     const int y = p / W, x = p - y * W;
     float g[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) g[c] = G[(size_t)c * n + p];
-    // weight gradient of this output pixel
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
       const int yy = clampi(y + ky - 1, 0, H - 1);
@@ -493,7 +534,6 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_res_bwd(Launch Lc, int r, int s
     }
 #pragma unroll
     for (int co = 0; co < 3; ++co) gw[81 + co] += g[co];
-    // input gradient of this pixel (gather over the pixels that read it)
     float acc[3] = {g[0], g[1], g[2]};
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
@@ -505,10 +545,10 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_res_bwd(Launch Lc, int r, int s
         const int cx = srcs(x, kx - 1, W, px);
         for (int a = 0; a < cy; ++a)
           for (int b = 0; b < cx; ++b) {
-            const int s = py[a] * W + px[b];
+            const int s2 = py[a] * W + px[b];
 #pragma unroll
             for (int co = 0; co < 3; ++co) {
-              const float gv = G[(size_t)co * n + s];
+              const float gv = G[(size_t)co * n + s2];
 #pragma unroll
               for (int ci = 0; ci < 3; ++ci) acc[ci] += Wr[(co * 3 + ci) * 9 + ky * 3 + kx] * gv;
             }
@@ -521,15 +561,15 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_res_bwd(Launch Lc, int r, int s
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < 84; ++q) {
-    const float s = wave_sum(gw[q]);
-    if (ln == 0) sh[q][wv] = s;
+    const float s2 = wave_sum(gw[q]);
+    if (ln == 0) sh[q][wv] = s2;
   }
   __syncthreads();
   if (threadIdx.x < 84) {
-    float s = 0.0f;
-    for (int w = 0; w < CC_PIX_TILE / 64; ++w) s += sh[threadIdx.x][w];
-    const ProdSeg& g = d->prod[d->prod_res0 + r];
-    d->wp[g.off + (size_t)wgi * 84 + threadIdx.x] = s;
+    float s2 = 0.0f;
+    for (int w2 = 0; w2 < CC_PIX_TILE / 64; ++w2) s2 += sh[threadIdx.x][w2];
+    const long long pg_off = d->prod[d->prod_res0 + r].off;
+    d->wp[pg_off + (size_t)wgi * 84 + threadIdx.x] = s2;
   }
 }
 
@@ -583,7 +623,7 @@ int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st) {
   return ok();
 }
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st) {
-  hipLaunchKernelGGL(k_ups_bwd, dim3(l.tile0[l.n]), dim3(CC_PIX_TILE), 0, st, l, j);
+  hipLaunchKernelGGL(k_ups_bwd, dim3(l.tile0[l.n]), dim3(256), 0, st, l, j);
   return ok();
 }
 int cc_launch_res_fwd(const Launch& l, int r, int last, int want_mse, hipStream_t st) {
