@@ -1,13 +1,18 @@
 """Throughput of the Cool-chic encode step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 One step = one full encoding iteration (training quantisation proxy, ARM
 entropy model and rate, upsampling, synthesis, MSE, backward, Adam) of one
 512x768 synthetic image with the 2,223-parameter decoder (s = 24 + F = 6
 inter-feature context, ARM 30-24-24-2 with stabilizer, synthesis 7-40-3 with
 stabilizer and two residual 3x3 layers), schedules of Table I mapped onto a
-1,000-iteration budget.  Inputs are resident in HBM before the timed region.
+1,000-iteration budget.  Both arithmetic forms are timed: `value` is the
+fused BF16 form (MLPs on MFMA in BF16 with FP32 accumulation, rate in FP32,
+totals in FP64); the plain FP32 form is reported beside it.  Also measured:
+a batched step over 16 images of uneven sizes, and a continuous-batching
+serving run over a finite Poisson trace (p50/p99 latency at a fixed
+iteration budget).  Inputs are resident in HBM before each timed region.
 Prints one JSON line.
 """
 import argparse
@@ -45,13 +50,106 @@ def arm_flops_per_step(mc, H, W):
     return tot
 
 
+def measure_step(precision, steps, warmup, timing=True):
+    import ctypes as C
+    import numpy as np
+    import torch
+    from paper_2605_02726_amd import _lib, workloads as wl
+    from paper_2605_02726_amd.encoder import Encoder, schedule
+
+    mc = wl.config_hop()
+    H, W, seed, lam, n_iter = 512, 768, 2, 1e-3, 1000
+    img = torch.from_numpy(wl.image_large(seed))
+    lat = np.zeros(wl.n_latents(mc, H, W), np.float32)
+    enc = Encoder(mc, img, lam, seed, lat, wl.init_params(mc, seed), precision=precision)
+    L = _lib.lib()
+    t = 0
+    for _ in range(warmup):
+        t += 1
+        enc.step(t, *schedule(t, n_iter), sync=False)
+    torch.cuda.synchronize()
+    if timing:
+        _lib.check(L.cc_timing_enable(b"arm"))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t += 1
+        enc.step(t, *schedule(t, n_iter), sync=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    arm_ms, arm_n = C.c_double(0.0), C.c_int(0)
+    if timing:
+        _lib.check(L.cc_timing_read(C.byref(arm_ms), C.byref(arm_n)))
+        _lib.check(L.cc_timing_enable(None))
+    loss, bits, mse = enc.eval_loss(t, *schedule(t, n_iter)[1:])
+    out = {"value": H * W * steps / dt / 1e6, "ms_per_step": 1e3 * dt / steps,
+           "loss": loss, "bits": bits, "mse": mse}
+    if arm_n.value:
+        out["arm_avg_ms"] = arm_ms.value / arm_n.value
+    del enc
+    return out
+
+
+def measure_batch(steps, warmup, precision="bf16", n=16):
+    """16 images of uneven sizes (sides uniform over multiples of 64 in
+    [256, 1536]), each with its own state, stepped in one set of launches."""
+    import numpy as np
+    import torch
+    from paper_2605_02726_amd import workloads as wl
+    from paper_2605_02726_amd.encoder import Encoder, schedule, step_batch, step_params
+
+    mc = wl.config_hop()
+    encs = []
+    for i, (H, W) in enumerate(wl.batch_shapes(n, seed=100)):
+        img = torch.from_numpy(wl.synth_image(H, W, 100 + i, n_rects=32))
+        encs.append(Encoder(mc, img, 1e-3, 100 + i, np.zeros(wl.n_latents(mc, H, W), np.float32),
+                            wl.init_params(mc, 100 + i), precision=precision))
+    px = sum(e.H * e.W for e in encs)
+    t = 0
+    for _ in range(warmup):
+        t += 1
+        step_batch(encs, [step_params(t, *schedule(t, 500))] * n, sync=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t += 1
+        step_batch(encs, [step_params(t, *schedule(t, 500))] * n, sync=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = {"value": px * steps / dt / 1e6, "unit": "Mpixel-iterations/s", "images": n,
+           "megapixels": round(px / 1e6, 3), "ms_per_step": round(1e3 * dt / steps, 4),
+           "precision": precision, "steps": steps}
+    del encs
+    return res
+
+
+def measure_serving(n_req, n_iter, rate_hz=8.0, precision="bf16"):
+    import numpy as np
+    from paper_2605_02726_amd import workloads as wl
+    from paper_2605_02726_amd.serve import Server, trace_jobs
+
+    mc = wl.config_hop()
+    jobs = trace_jobs(n_req, rate_hz, seed=7, lo=256, hi=2048, n_iter=n_iter, mc=mc)
+    srv = Server(mc, precision=precision, check_every=100)
+    srv.run(jobs)
+    st = srv.stats()
+    mean_px = float(np.mean([j.image.shape[1] * j.image.shape[2] for j in jobs]))
+    st.update({"requests": n_req, "iterations_per_request": n_iter, "rate_hz": rate_hz,
+               "offered_mpx_it_s": rate_hz * n_iter * mean_px / 1e6,
+               "sides": "multiples of 64 in [256, 2048]", "lambdas": [1e-4, 4e-4, 1e-3, 4e-3],
+               "precision": precision})
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp32", "bf16"])
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for cpu_baseline (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=20, help="batched-step timing (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=16, help="serving trace length (0 = skip)")
+    ap.add_argument("--serve-iters", type=int, default=2000)
     ap.add_argument("--no-kernel-timing", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -59,71 +157,51 @@ def main():
                           "data-parallel inside one MI355X; --gpus must be 1"}))
         sys.exit(2)
 
-    import ctypes as C
-    import numpy as np
     import torch
-
-    from paper_2605_02726_amd import _lib, workloads as wl
-    from paper_2605_02726_amd.encoder import Encoder, schedule
-
+    from paper_2605_02726_amd import workloads as wl
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+
+    forms = {}
+    for p in (["fp32", "bf16"] if args.precision == "both" else [args.precision]):
+        forms[p] = measure_step(p, args.steps, args.warmup, not args.no_kernel_timing)
+    head = "bf16" if "bf16" in forms else "fp32"
+    main_f = forms[head]
+
     mc = wl.config_hop()
-    H, W, seed, lam, n_iter = 512, 768, 2, 1e-3, 1000
-    img = torch.from_numpy(wl.image_large(seed))
-    lat = np.zeros(wl.n_latents(mc, H, W), np.float32)
-    par = wl.init_params(mc, seed)
-    enc = Encoder(mc, img, lam, seed, lat, par, precision=args.precision)
-    L = _lib.lib()
-
-    t = 0
-    for _ in range(args.warmup):
-        t += 1
-        lr, T, s = schedule(t, n_iter)
-        enc.step(t, lr, T, s, sync=False)
-    torch.cuda.synchronize()
-    if not args.no_kernel_timing:
-        _lib.check(L.cc_timing_enable(b"arm"))
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        t += 1
-        lr, T, s = schedule(t, n_iter)
-        enc.step(t, lr, T, s, sync=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    arm_ms, arm_n = C.c_double(0.0), C.c_int(0)
-    if not args.no_kernel_timing:
-        _lib.check(L.cc_timing_read(C.byref(arm_ms), C.byref(arm_n)))
-        _lib.check(L.cc_timing_enable(None))
-    loss, bits, mse = enc.eval_loss(t, T, s)
-
-    ms_step = 1e3 * dt / args.steps
-    value = H * W * args.steps / dt / 1e6
+    H, W = 512, 768
     flops = arm_flops_per_step(mc, H, W)
     roof = None
-    if arm_n.value:
-        avg_s = arm_ms.value / arm_n.value / 1e3
-        if args.precision == "fp32":
-            achieved = flops / avg_s / 1e12
-            roof = {"kernel": "arm_fwd_rate_bwd", "bound": "alu", "achieved": round(achieved, 3),
-                    "peak": PEAKS["fp32_valu_TFLOPs"], "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAKS["fp32_valu_TFLOPs"], 4), "traffic": None,
-                    "avg_launch_ms": round(1e3 * avg_s, 4), "flops_per_launch": flops}
-        else:
-            achieved = flops / avg_s / 1e12
-            roof = {"kernel": "arm_fwd_rate_bwd", "bound": "mfma", "achieved": round(achieved, 3),
-                    "peak": PEAKS["bf16_mfma_TFLOPs"], "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAKS["bf16_mfma_TFLOPs"], 4), "traffic": None,
-                    "avg_launch_ms": round(1e3 * avg_s, 4), "flops_per_launch": flops}
+    if "arm_avg_ms" in main_f:
+        avg_s = main_f["arm_avg_ms"] / 1e3
+        achieved = flops / avg_s / 1e12
+        peak = PEAKS["bf16_mfma_TFLOPs"] if head == "bf16" else PEAKS["fp32_valu_TFLOPs"]
+        roof = {"kernel": "arm_fused_fwd_rate_bwd" if head == "bf16" else "arm_plain_fwd_rate_bwd",
+                "bound": "mfma" if head == "bf16" else "alu", "achieved": round(achieved, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                "traffic": None, "avg_launch_ms": round(1e3 * avg_s, 4),
+                "flops_per_launch": flops}
+        if "fp32" in forms and "arm_avg_ms" in forms["fp32"]:
+            a32 = flops / (forms["fp32"]["arm_avg_ms"] / 1e3) / 1e12
+            roof["fp32_plain_kernel"] = {"bound": "alu", "achieved": round(a32, 3),
+                                         "peak": PEAKS["fp32_valu_TFLOPs"],
+                                         "frac": round(a32 / PEAKS["fp32_valu_TFLOPs"], 4),
+                                         "avg_launch_ms": round(forms["fp32"]["arm_avg_ms"], 4)}
+
+    batched = measure_batch(args.batch_steps, 3) if args.batch_steps > 0 else None
+    serving = measure_serving(args.serve_requests, args.serve_iters) if args.serve_requests > 0 else None
 
     cpu = None
     if args.cpu_steps > 0:
+        import numpy as np
         from oracle import coolchic_ref as R
+        from paper_2605_02726_amd.encoder import schedule
         torch.set_num_threads(os.cpu_count() or 1)
-        ost = R.OracleState(mc.as_dict(), H, W, wl.image_large(seed), lam, seed, lat, par)
-        ost.step(1, *schedule(1, n_iter))     # first call pays one-off costs
+        lat = np.zeros(wl.n_latents(mc, H, W), np.float32)
+        ost = R.OracleState(mc.as_dict(), H, W, wl.image_large(2), 1e-3, 2, lat, wl.init_params(mc, 2))
+        ost.step(1, *schedule(1, 1000))     # first call pays one-off costs
         c0 = time.perf_counter()
         for tt in range(2, 2 + args.cpu_steps):
-            ost.step(tt, *schedule(tt, n_iter))
+            ost.step(tt, *schedule(tt, 1000))
         cdt = time.perf_counter() - c0
         cpu = {"value": round(H * W * args.cpu_steps / cdt / 1e6, 4),
                "unit": "Mpixel-iterations/s", "cores": torch.get_num_threads(), "kind": "oracle",
@@ -132,24 +210,29 @@ def main():
 
     out = {
         "metric": "Mpixel-iterations/s (fwd+bwd+Adam)",
-        "value": round(value, 3),
+        "value": round(main_f["value"], 3),
         "unit": "Mpixel-iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(main_f["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16",
+        "dtype": "bf16" if head == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": "encode step, one 512x768 RGB image, 2223-parameter decoder "
                                "(s=24+F=6 ARM 30-24-24-2, synthesis 7-40-3, 2 residual 3x3)",
-                   "global_batch": 1, "precision_form": args.precision,
-                   "final_loss": loss, "final_bits": bits, "final_mse": mse},
+                   "global_batch": 1},
+        "forms": {p: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in f.items()}
+                  for p, f in forms.items()},
         "roofline": roof,
+        "batched_16_images": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
+    if "fp32" in forms and "bf16" in forms:
+        out["bf16_speedup_vs_fp32"] = round(forms["bf16"]["value"] / forms["fp32"]["value"], 3)
     print(json.dumps(out), flush=True)
 
 

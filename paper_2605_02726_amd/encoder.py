@@ -172,7 +172,11 @@ def step_batch(encoders: Sequence[Encoder], params: Sequence[_lib.cc_step_params
     hs = (C.c_void_p * n)(*[e.handle.value for e in encoders])
     ps = (_lib.cc_step_params * n)(*params)
     out = (C.c_double * (3 * n))() if sync else None
-    check(lib().cc_encode_step_batch(hs, n, ps, out, _stream()))
+    rc = lib().cc_encode_step_batch(hs, n, ps, out, _stream())
+    if rc == _lib.CC_ENONFINITE and sync:
+        # every state's totals were read; the caller finds the non-finite ones
+        return [tuple(out[3 * i:3 * i + 3]) for i in range(n)]
+    check(rc)
     if not sync:
         return None
     return [tuple(out[3 * i:3 * i + 3]) for i in range(n)]
