@@ -154,6 +154,36 @@ int cc_debug_read(cc_state* s, const char* buffer, float* host, int64_t count, v
 /* Switch the arithmetic of the MLP kernels (CC_FP32_PLAIN / CC_BF16_FUSED). */
 int cc_set_precision(cc_state* s, int precision);
 
+/* Per-module forward and backward on caller buffers (for autograd
+ * wrappers).  The state supplies the decoder shape and serves as workspace:
+ * its latent, parameter and scratch buffers are overwritten, so run these on a
+ * state that is not being encoded, and call a module's backward right after
+ * its forward on the same state.  `params` / `grad_params`: the full decoder
+ * parameter vector (cc_n_params floats, documented order); a backward writes
+ * only its module's range of grad_params.  Any gradient pointer may be NULL.
+ *
+ * ARM (Section III-A, eq. factorized-probability and eq.
+ * laplace-distribution): bits = sum over all latents of -log2 of the
+ * Laplace bin probability given the causal and inter-feature context, for
+ * given quantised latents `yhat` (flat pyramid, cc_n_latents floats); with
+ * gradient pointers also d bits / d yhat and d bits / d (ARM, IFCE
+ * parameters).  bits_out: host double (the stream is synchronised).
+ *
+ * Upsampling (Section III-B): zhat [L, H, W] = f_upsilon(yhat); the backward
+ * takes d/d zhat and writes d/d yhat (cc_n_latents) and the tap gradients.
+ *
+ * Synthesis (Sections III-B, III-C): xhat [3, H, W] = f_theta(zhat) (trunk,
+ * stabilizer, residual layers); the backward takes d/d xhat and writes
+ * d/d zhat [L, H, W] and the synthesis parameter gradients. */
+int cc_arm_fwd_bwd(cc_state* s, const float* yhat, const float* params, double* bits_out,
+                   float* grad_yhat, float* grad_params, void* stream);
+int cc_ups_fwd(cc_state* s, const float* yhat, const float* params, float* zhat, void* stream);
+int cc_ups_bwd(cc_state* s, const float* grad_zhat, float* grad_yhat, float* grad_params,
+               void* stream);
+int cc_syn_fwd(cc_state* s, const float* zhat, const float* params, float* xhat, void* stream);
+int cc_syn_bwd(cc_state* s, const float* grad_xhat, float* grad_zhat, float* grad_params,
+               void* stream);
+
 /* Live kernel timing for measurement tools: HIP events are recorded on the
  * launch stream around every launch of one kernel class ("arm", "syn_bwd",
  * "ups_bwd", "join", "adam"; NULL or "" switches timing off) by the calls

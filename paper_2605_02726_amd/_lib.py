@@ -69,6 +69,12 @@ _PROTOS = [
     ("cc_get_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cc_set_precision", C.c_int, [C.c_void_p, C.c_int]),
     ("cc_debug_read", C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    ("cc_arm_fwd_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cc_ups_fwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cc_ups_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cc_syn_fwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("cc_syn_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cc_timing_enable", C.c_int, [C.c_char_p]),
     ("cc_timing_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     ("cc_free_state", None, [C.c_void_p]),

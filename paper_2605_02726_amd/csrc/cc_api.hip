@@ -844,6 +844,157 @@ int cc_get_grad(cc_state* s, float* grad_host, void* stream) {
   return CC_OK;
 }
 
+// ------------------------------------------------- per-module entry points
+namespace {
+
+int module_check(cc_state* s) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  return CC_OK;
+}
+
+int copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (!bytes) return CC_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+  return CC_OK;
+}
+
+// Load the caller's decoder parameters, then run the weight-gradient
+// reduction and copy parameter range [b, e) of the gradient out.
+int params_grad_out(cc_state* s, float* out, int b, int e, hipStream_t st) {
+  const DevDesc& h = s->lo.h;
+  cc_state* one[1] = {s};
+  const Launch w1 = plan(one, 1, [](const DevDesc& x) { return cdiv(x.n_par, 64) * CC_WRED_SPLIT; });
+  const Launch w2 = plan(one, 1, [](const DevDesc& x) { return cdiv(x.n_par, CC_ELT_TILE); });
+  RET(cc_launch_wreduce(w1, w2, st));
+  return copy_d2d(out + b, h.grad + h.n_lat + b, sizeof(float) * (e - b), st);
+}
+
+}  // namespace
+
+int cc_arm_fwd_bwd(cc_state* s, const float* yhat, const float* params, double* bits_out,
+                   float* grad_yhat, float* grad_params, void* stream) {
+  int rc = module_check(s);
+  if (rc != CC_OK) return rc;
+  if (!yhat || !params) return fail(CC_EINVAL, "yhat and params are required");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  cc_state* one[1] = {s};
+  const bool bwd = grad_yhat || grad_params;
+  RET(copy_d2d(h.yhat, yhat, sizeof(float) * h.n_lat, st));
+  RET(copy_d2d(h.theta + h.n_lat, params, sizeof(float) * h.n_par, st));
+  // gradients of the bits themselves: rate scale 1
+  RET(cc_launch_poke(&s->ddev->rate_scale, 1.0f, st));
+  rc = arm(one, 1, bwd ? 1 : 0, st);
+  if (rc == CC_OK && bwd && h.G > 0) {
+    for (int f = 1; f < h.L && rc == CC_OK; ++f) {
+      const Launch l = plan(one, 1, [f](const DevDesc& x) {
+        long long tot = 0;
+        for (int c = 0; c < x.G; ++c)
+          if (c + f <= x.L - 1) tot += (long long)x.F * x.gh[c + f] * x.gw[c + f];
+        return cdiv(tot, CC_ELT_TILE);
+      });
+      rc = cc_launch_pool(l, f, st);
+    }
+  }
+  if (rc == CC_OK && grad_yhat)
+    rc = cc_launch_join(plan(one, 1, [](const DevDesc& x) { return x.lat_ntile; }), st, grad_yhat);
+  const int rc2 = cc_launch_poke(&s->ddev->rate_scale, h.rate_scale, st);
+  if (rc != CC_OK || rc2 != CC_OK) return fail(CC_EDEVICE, "ARM module launch failed");
+  if (grad_params) RET(params_grad_out(s, grad_params, 0, h.n_arm_par, st));
+  Launch lr;
+  memset(&lr, 0, sizeof lr);
+  lr.n = 1;
+  lr.d[0] = s->ddev;
+  RET(cc_launch_lreduce(lr, st));
+  if (bits_out) {
+    double sc[4];
+    HIPCHK(hipMemcpyAsync(sc, h.scal, sizeof sc, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *bits_out = sc[1];
+  }
+  return CC_OK;
+}
+
+int cc_ups_fwd(cc_state* s, const float* yhat, const float* params, float* zhat, void* stream) {
+  int rc = module_check(s);
+  if (rc != CC_OK) return rc;
+  if (!yhat || !params || !zhat) return fail(CC_EINVAL, "null pointer");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  cc_state* one[1] = {s};
+  const size_t npx = (size_t)h.H * h.W;
+  RET(copy_d2d(h.yhat, yhat, sizeof(float) * h.n_lat, st));
+  RET(copy_d2d(h.theta + h.n_lat, params, sizeof(float) * h.n_par, st));
+  for (int j = h.L - 1; j >= 1; --j) {
+    const Launch l = plan(one, 1, [j](const DevDesc& x) { return cdiv(x.gh[j - 1] * x.gw[j - 1], CC_PIX_TILE); });
+    RET(cc_launch_ups_fwd(l, j, st));
+  }
+  RET(copy_d2d(zhat, h.yhat, sizeof(float) * npx, st));
+  return copy_d2d(zhat + npx, h.U + h.uoff[1], sizeof(float) * (h.L - 1) * npx, st);
+}
+
+int cc_ups_bwd(cc_state* s, const float* grad_zhat, float* grad_yhat, float* grad_params, void* stream) {
+  int rc = module_check(s);
+  if (rc != CC_OK) return rc;
+  if (!grad_zhat) return fail(CC_EINVAL, "null pointer");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  cc_state* one[1] = {s};
+  const size_t npx = (size_t)h.H * h.W;
+  RET(copy_d2d(h.dyq, grad_zhat, sizeof(float) * npx, st));
+  RET(copy_d2d(h.dU + h.uoff[1], grad_zhat + npx, sizeof(float) * (h.L - 1) * npx, st));
+  for (int j = 1; j < h.L; ++j) {
+    const Launch l = plan(one, 1, [j](const DevDesc& x) {
+      return cdiv(x.gh[j], CC_UPS_TILE) * cdiv(x.gw[j], CC_UPS_TILE);
+    });
+    RET(cc_launch_ups_bwd(l, j, st));
+  }
+  if (grad_yhat) RET(copy_d2d(grad_yhat, h.dyq, sizeof(float) * h.n_lat, st));
+  if (grad_params) RET(params_grad_out(s, grad_params, h.p_ups[1], h.p_ups[1] + 4 * (h.L - 1), st));
+  return CC_OK;
+}
+
+int cc_syn_fwd(cc_state* s, const float* zhat, const float* params, float* xhat, void* stream) {
+  int rc = module_check(s);
+  if (rc != CC_OK) return rc;
+  if (!zhat || !params || !xhat) return fail(CC_EINVAL, "null pointer");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  cc_state* one[1] = {s};
+  const size_t npx = (size_t)h.H * h.W;
+  RET(copy_d2d(h.yhat, zhat, sizeof(float) * npx, st));
+  RET(copy_d2d(h.U + h.uoff[1], zhat + npx, sizeof(float) * (h.L - 1) * npx, st));
+  RET(copy_d2d(h.theta + h.n_lat, params, sizeof(float) * h.n_par, st));
+  const Launch lp = plan(one, 1, [](const DevDesc& x) { return x.pix_ntile; });
+  RET(cc_launch_syn_fwd_plain(lp, h, 0, st));
+  for (int r = 0; r < h.n_res; ++r) RET(cc_launch_res_fwd(lp, r, r == h.n_res - 1, 0, st));
+  return copy_d2d(xhat, h.X + (size_t)h.n_res * 3 * npx, sizeof(float) * 3 * npx, st);
+}
+
+int cc_syn_bwd(cc_state* s, const float* grad_xhat, float* grad_zhat, float* grad_params, void* stream) {
+  int rc = module_check(s);
+  if (rc != CC_OK) return rc;
+  if (!grad_xhat) return fail(CC_EINVAL, "null pointer");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  cc_state* one[1] = {s};
+  const size_t npx = (size_t)h.H * h.W;
+  RET(copy_d2d(h.dXa, grad_xhat, sizeof(float) * 3 * npx, st));
+  const Launch lr = plan(one, 1, [](const DevDesc& x) { return x.res_nwg; });
+  int src_b = 0;
+  for (int r = h.n_res - 1; r >= 0; --r) {
+    RET(cc_launch_res_bwd2(lr, r, src_b, st));
+    src_b ^= 1;
+  }
+  RET(cc_launch_syn_bwd_plain(plan(one, 1, [](const DevDesc& x) { return x.syn_nwg; }), h, src_b, st));
+  if (grad_zhat) {
+    RET(copy_d2d(grad_zhat, h.dyq, sizeof(float) * npx, st));
+    RET(copy_d2d(grad_zhat + npx, h.dU + h.uoff[1], sizeof(float) * (h.L - 1) * npx, st));
+  }
+  if (grad_params) RET(params_grad_out(s, grad_params, h.p_sw[0], h.n_par, st));
+  return CC_OK;
+}
+
 int cc_debug_read(cc_state* s, const char* buffer, float* host, int64_t count, void* stream) {
   if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
   if (!buffer || !host || count < 0) return fail(CC_EINVAL, "bad arguments");

@@ -100,7 +100,8 @@ int cc_launch_set_step(const StepLaunch& s, hipStream_t st);
 int cc_launch_qtrain(const Launch& l, hipStream_t st);
 int cc_launch_arm(const Launch& l, const DevDesc& h, int bwd, int precision, hipStream_t st);
 int cc_launch_pool(const Launch& l, int f, hipStream_t st);
-int cc_launch_join(const Launch& l, hipStream_t st);
+int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out = nullptr);
+int cc_launch_poke(float* p, float v, hipStream_t st);
 int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_syn_fwd(const Launch& l, const DevDesc& h, int final_mse, int precision, hipStream_t st);

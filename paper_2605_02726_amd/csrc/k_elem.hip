@@ -133,7 +133,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L, int f) {
 // where d rate / d yhat gathers, in a fixed order, the direct term, the
 // context gradients of the positions that use this latent as a causal
 // neighbour (reversed offsets) and the IFCE gradients of finer grids.
-__global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L) {
+__global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only_out) {
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
   const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
@@ -165,9 +165,15 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L) {
     const float* D = d->df + d->dfoff[c][k - c];
     for (int f = 0; f < d->F; ++f) g += W[f * nin + q] * D[f * nk + li];
   }
+  if (rate_only_out) {
+    rate_only_out[i] = g;
+    return;
+  }
   g += d->dyq[i];
   d->grad[i] = g * d->dq[i];
 }
+
+__global__ void k_poke(float* p, float v) { *p = v; }
 
 // Adam (Kingma and Ba) over theta = [latents, parameters]; latents are left
 // untouched when frozen.
@@ -283,8 +289,12 @@ int cc_launch_pool(const Launch& l, int f, hipStream_t st) {
   hipLaunchKernelGGL(k_pool, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, f);
   return check_launch();
 }
-int cc_launch_join(const Launch& l, hipStream_t st) {
-  hipLaunchKernelGGL(k_join, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l);
+int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out) {
+  hipLaunchKernelGGL(k_join, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, rate_only_out);
+  return check_launch();
+}
+int cc_launch_poke(float* p, float v, hipStream_t st) {
+  hipLaunchKernelGGL(k_poke, dim3(1), dim3(1), 0, st, p, v);
   return check_launch();
 }
 int cc_launch_adam(const Launch& l, hipStream_t st) {

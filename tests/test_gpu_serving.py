@@ -49,7 +49,7 @@ def test_server_results_equal_alone(precision):
 def test_server_hbm_budget_serialises_admission():
     from paper_2605_02726_amd.encoder import state_bytes
     from paper_2605_02726_amd.serve import Server
-    mc, jobs = _jobs(n_iter=10)
+    mc, jobs = _jobs(n_iter=10, arrivals=(0.0, 0.0, 0.0, 0.0))
     biggest = max(state_bytes(mc, j.image.shape[1], j.image.shape[2], "bf16") for j in jobs)
     srv = Server(mc, precision="bf16", hbm_budget=biggest, check_every=5)
     done = srv.run(jobs)
