@@ -41,6 +41,23 @@ __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// Data-path products in split BF16: x = hi + lo for both the weights and the
+// activations, accumulating hi*hi + hi*lo + lo*hi (about 16 significant bits
+// per product, FP32 accumulation).
+__device__ __forceinline__ f32x16 mfma3(bf16x8 wh, bf16x8 wl, bf16x8 bh, bf16x8 bl, f32x16 c) {
+  c = mfma(wl, bh, c);
+  c = mfma(wh, bl, c);
+  return mfma(wh, bh, c);
+}
+
+__device__ __forceinline__ void split8(const float* x, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    hi[i] = (__bf16)x[i];
+    lo[i] = (__bf16)(x[i] - (float)hi[i]);
+  }
+}
+
 // Row of the 32x32 output held by accumulator register i of a lane in half h.
 __device__ __forceinline__ int mrow(int i, int h) { return (i >> 2) * 8 + 4 * h + (i & 3); }
 // Hidden unit carried at K index k when the previous layer's output
@@ -98,14 +115,19 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 + CC_MAX_L - 1 <= 32, "shape");
   __shared__ float ywin[HALO + TH][WR];
   __shared__ float acc[HALO + TH][WR];
-  __shared__ Tile tg[3][NW], tc[3][NW];
+  // per-wave transposing tiles; the end-of-kernel weight-gradient sum reuses
+  // the same storage
+  __shared__ __attribute__((aligned(16))) char tiles_raw[2 * 3 * NW * sizeof(Tile)];
+  Tile(*tg)[NW] = reinterpret_cast<Tile(*)[NW]>(tiles_raw);
+  Tile(*tc)[NW] = reinterpret_cast<Tile(*)[NW]>(tiles_raw + 3 * NW * sizeof(Tile));
+  float(*wsum)[32][33] = reinterpret_cast<float(*)[32][33]>(tiles_raw);
+  static_assert(3 * 32 * 33 * sizeof(float) <= 2 * 3 * NW * sizeof(Tile), "wsum alias");
   __shared__ float pwin[CC_MAX_L - 1][SW / 2 + 1];   // IFCE parents of the segment
-  __shared__ float wsum[3][32][33];
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
   __shared__ int soff[32];          // context slot -> LDS offset of its neighbour
   __shared__ double bsh[NW];
   __shared__ float carry[HALO + TH][2 * HALO];
-  __shared__ bf16x8 wop[4][2][64];
+  __shared__ bf16x8 wop[4][2][64], wopl[4][2][64];
 
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
@@ -159,6 +181,19 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
       wop[1][s][lane] = a2;
       wop[2][s][lane] = a2t;
       wop[3][s][lane] = a1t;
+      bf16x8 l1, l2, l2t, l1t;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int kk = 16 * s + 8 * hh + i, u = kunit(kk), m = n;
+        l1[i] = (__bf16)((m < H1 && kk < CTX) ? W1[m * CTX + kk] - (float)a1[i] : 0.0f);
+        l2[i] = (__bf16)((m < H2 && u < H1) ? W2[m * H1 + u] - (float)a2[i] : 0.0f);
+        l2t[i] = (__bf16)((m < H1 && u < H2) ? W2[u * H1 + m] - (float)a2t[i] : 0.0f);
+        l1t[i] = (__bf16)((m < CTX && u < H1) ? W1[u * CTX + m] - (float)a1t[i] : 0.0f);
+      }
+      wopl[0][s][lane] = l1;
+      wopl[1][s][lane] = l2;
+      wopl[2][s][lane] = l2t;
+      wopl[3][s][lane] = l1t;
     }
   }
   const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
@@ -227,11 +262,9 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
           }
           cf[s][i] = v;
         }
-      bf16x8 bc[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) bc[s][i] = (__bf16)cf[s][i];
+      bf16x8 bc[2], bcl[2];
+      split8(cf[0], bc[0], bcl[0]);
+      split8(cf[1], bc[1], bcl[1]);
       const bool do_bwd = bwd > 0;
       if (do_bwd) {
         // weight-gradient columns known after the context: [context | 1]
@@ -255,23 +288,27 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
       }
       // ---- layer 1 and 2
       f32x16 z = {};
-      f32x16 D = mfma(wop[0][0][lane], bc[0], z);
-      if (CTX > 16) D = mfma(wop[0][1][lane], bc[1], D);
+      f32x16 D = mfma3(wop[0][0][lane], wopl[0][0][lane], bc[0], bcl[0], z);
+      if (CTX > 16) D = mfma3(wop[0][1][lane], wopl[0][1][lane], bc[1], bcl[1], D);
       unsigned m1 = 0, m2 = 0;
-      bf16x8 bh[2];
+      bf16x8 bh[2], bhl[2];
+      {
+        float hv[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const float v = fmaxf(D[i] + vec[0][mrow(i, hh)], 0.0f);
-        m1 |= (v > 0.0f ? 1u : 0u) << i;
-        bh[i >> 3][i & 7] = (__bf16)v;
+        for (int i = 0; i < 16; ++i) {
+          hv[i] = fmaxf(D[i] + vec[0][mrow(i, hh)], 0.0f);
+          m1 |= (hv[i] > 0.0f ? 1u : 0u) << i;
+        }
+        split8(hv, bh[0], bhl[0]);
+        split8(hv + 8, bh[1], bhl[1]);
       }
       if (do_bwd) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) C2.v[mrow(i, hh)][n] = bh[i >> 3][i & 7];
         if (hh == 0) C2.v[H1][n] = (__bf16)1.0f;
       }
-      D = mfma(wop[1][0][lane], bh[0], z);
-      D = mfma(wop[1][1][lane], bh[1], D);
+      D = mfma3(wop[1][0][lane], wopl[1][0][lane], bh[0], bhl[0], z);
+      D = mfma3(wop[1][1][lane], wopl[1][1][lane], bh[1], bhl[1], D);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const float v = fmaxf(D[i] + vec[1][mrow(i, hh)], 0.0f);
@@ -311,27 +348,34 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
 
       // ---- backward
       const float dmu = -gd * rs, dl = gl * rs;
-      bf16x8 bd[2];
+      bf16x8 bd[2], bdl[2];
+      {
+        float gv[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const float v = ((m2 >> i) & 1u) ? vec[2][mrow(i, hh)] * dmu + vec[3][mrow(i, hh)] * dl : 0.0f;
-        bd[i >> 3][i & 7] = (__bf16)v;
-        G2.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
+        for (int i = 0; i < 16; ++i)
+          gv[i] = ((m2 >> i) & 1u) ? vec[2][mrow(i, hh)] * dmu + vec[3][mrow(i, hh)] * dl : 0.0f;
+        split8(gv, bd[0], bdl[0]);
+        split8(gv + 8, bd[1], bdl[1]);
       }
-      D = mfma(wop[2][0][lane], bd[0], z);
-      D = mfma(wop[2][1][lane], bd[1], D);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const float v = ((m1 >> i) & 1u) ? D[i] : 0.0f;
-        bd[i >> 3][i & 7] = (__bf16)v;
-        G1.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
+      for (int i = 0; i < 16; ++i) G2.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
+      D = mfma3(wop[2][0][lane], wopl[2][0][lane], bd[0], bdl[0], z);
+      D = mfma3(wop[2][1][lane], wopl[2][1][lane], bd[1], bdl[1], D);
+      {
+        float gv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) gv[i] = ((m1 >> i) & 1u) ? D[i] : 0.0f;
+        split8(gv, bd[0], bdl[0]);
+        split8(gv + 8, bd[1], bdl[1]);
       }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) G1.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
       if (hh == 0) {
         G1.v[H1][n] = (__bf16)dmu;
         G1.v[H1 + 1][n] = (__bf16)dl;
       }
-      D = mfma(wop[3][0][lane], bd[0], z);
-      D = mfma(wop[3][1][lane], bd[1], D);
+      D = mfma3(wop[3][0][lane], wopl[3][0][lane], bd[0], bdl[0], z);
+      D = mfma3(wop[3][1][lane], wopl[3][1][lane], bd[1], bdl[1], D);
       float dc[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
