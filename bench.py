@@ -33,6 +33,13 @@ PEAKS = {
     "fp32_valu_TFLOPs": 78.6,
 }
 
+# HBM bytes per launch of the fused BF16 ARM kernel on the 512x768 workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by a plain-copy
+# calibration (FETCH x2.000, WRITE x1.000); the commands and the table are in
+# profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
+# until the counters are taken again.
+ARM_FUSED_TRAFFIC_BYTES = int((2.0 * 3585.0 + 1.0 * 18675.4) * 1024)
+
 
 def arm_flops_per_step(mc, H, W):
     """Algorithmic FLOPs of the ARM forward + rate-gradient backward + weight
@@ -87,6 +94,64 @@ def measure_step(precision, steps, warmup, timing=True):
         out["arm_avg_ms"] = arm_ms.value / arm_n.value
     del enc
     return out
+
+
+def hbm_bytes_per_step(mc, H, W):
+    """Algorithmic HBM bytes per launch-group of the HBM-bound kernels of one
+    512x768 step (each array read or written once, FP32)."""
+    L = mc.L
+    n = [(H >> k) * (W >> k) for k in range(L)]
+    n_lat = sum(n)
+    n_par = None
+    from paper_2605_02726_amd import workloads as wl
+    n_par = wl.n_params(mc)
+    ups_fwd = sum(4 * ((L - j) * n[j] + (L - j) * n[j - 1]) for j in range(1, L))
+    ups_bwd = sum(4 * ((L - j) * n[j - 1] + 2 * (L - j) * n[j]) for j in range(1, L))
+    return {
+        "adam": 28 * (n_lat + n_par),                  # read theta, g, m, v; write theta, m, v
+        "ups_fwd": ups_fwd,                            # read T_j, write U_j (all levels)
+        "ups_bwd": ups_bwd,                            # read dU_j and T_j, write dT_j (all levels)
+        "join": 4 * n_lat * 6,                         # rate planes (3), distortion grad, dq; write grad
+    }
+
+
+def measure_kernel(precision, kernel, steps=20, warmup=3):
+    """Average duration (ms) per step of one kernel class, live with HIP
+    events on the launch stream."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    from paper_2605_02726_amd import _lib, workloads as wl
+    from paper_2605_02726_amd.encoder import Encoder, schedule
+    mc = wl.config_hop()
+    H, W = 512, 768
+    enc = Encoder(mc, torch.from_numpy(wl.image_large(2)), 1e-3, 2,
+                  np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, 2),
+                  precision=precision)
+    L = _lib.lib()
+    for t in range(1, warmup + 1):
+        enc.step(t, *schedule(t, 1000), sync=False)
+    _lib.check(L.cc_timing_enable(kernel.encode()))
+    for t in range(warmup + 1, warmup + steps + 1):
+        enc.step(t, *schedule(t, 1000), sync=False)
+    torch.cuda.synchronize()
+    ms, cnt = C.c_double(0.0), C.c_int(0)
+    _lib.check(L.cc_timing_read(C.byref(ms), C.byref(cnt)))
+    _lib.check(L.cc_timing_enable(None))
+    del enc
+    return ms.value / steps
+
+
+def copy_calibration(mib=512, reps=5):
+    """Plain device copies of known size, for scaling rocprof FETCH_SIZE /
+    WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes": mib << 20, "reps": reps}
 
 
 def measure_batch(steps, warmup, precision="bf16", n=16):
@@ -151,7 +216,18 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=16, help="serving trace length (0 = skip)")
     ap.add_argument("--serve-iters", type=int, default=2000)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--only-step", action="store_true",
+                    help="time only the single-image step (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run 512 MiB device copies only (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration()))
+        return
+    if args.only_step:
+        args.batch_steps = 0
+        args.serve_requests = 0
+        args.cpu_steps = 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the per-image encode step is "
                           "data-parallel inside one MI355X; --gpus must be 1"}))
@@ -178,7 +254,8 @@ def main():
         roof = {"kernel": "arm_fused_fwd_rate_bwd" if head == "bf16" else "arm_plain_fwd_rate_bwd",
                 "bound": "mfma" if head == "bf16" else "alu", "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-                "traffic": None, "avg_launch_ms": round(1e3 * avg_s, 4),
+                "traffic": ARM_FUSED_TRAFFIC_BYTES if head == "bf16" else None,
+                "traffic_unit": "bytes per launch", "avg_launch_ms": round(1e3 * avg_s, 4),
                 "flops_per_launch": flops}
         if "fp32" in forms and "arm_avg_ms" in forms["fp32"]:
             a32 = flops / (forms["fp32"]["arm_avg_ms"] / 1e3) / 1e12
@@ -187,6 +264,16 @@ def main():
                                          "frac": round(a32 / PEAKS["fp32_valu_TFLOPs"], 4),
                                          "avg_launch_ms": round(forms["fp32"]["arm_avg_ms"], 4)}
 
+    hbm = None
+    if not args.no_kernel_timing and not args.only_step:
+        bts = hbm_bytes_per_step(mc, H, W)
+        hbm = {}
+        for name in ("adam", "ups_fwd", "ups_bwd", "join"):
+            ms = measure_kernel(head, name)
+            hbm[name] = {"ms_per_step": round(ms, 4), "bytes_per_step": bts[name],
+                         "achieved_GBs": round(bts[name] / (ms / 1e3) / 1e9, 1),
+                         "peak_GBs": PEAKS["hbm_GBs"],
+                         "frac": round(bts[name] / (ms / 1e3) / 1e9 / PEAKS["hbm_GBs"], 4)}
     batched = measure_batch(args.batch_steps, 3) if args.batch_steps > 0 else None
     serving = measure_serving(args.serve_requests, args.serve_iters) if args.serve_requests > 0 else None
 
@@ -227,6 +314,7 @@ def main():
         "forms": {p: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in f.items()}
                   for p, f in forms.items()},
         "roofline": roof,
+        "hbm_kernels": hbm,
         "batched_16_images": batched,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -502,7 +502,7 @@ int set_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st)
 
 // Optional live timing of one kernel class with HIP events recorded on the
 // launch stream around each of its launches (see cc_timing_enable).
-enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_ADAM = 3, TK_UPS_BWD = 4, TK_JOIN = 5 };
+enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_ADAM = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6 };
 struct Timing {
   int kind = TK_NONE;
   std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -546,9 +546,12 @@ int arm(cc_state* const* s, int n, int bwd, hipStream_t st) {
 // (+ MSE when want_mse).
 int forward_dist(cc_state* const* s, int n, int want_mse, hipStream_t st) {
   const DevDesc& h0 = s[0]->lo.h;
-  for (int j = h0.L - 1; j >= 1; --j) {
-    const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j - 1] * h.gw[j - 1], CC_PIX_TILE); });
-    RET(cc_launch_ups_fwd(l, j, st));
+  {
+    TimeScope ts(TK_UPS_FWD, st);
+    for (int j = h0.L - 1; j >= 1; --j) {
+      const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j - 1] * h.gw[j - 1], CC_PIX_TILE); });
+      RET(cc_launch_ups_fwd(l, j, st));
+    }
   }
   const Launch lp = plan(s, n, [](const DevDesc& h) { return h.pix_ntile; });
   RET(cc_launch_syn_fwd_plain(lp, h0, (h0.n_res == 0 && want_mse) ? 1 : 0, st));
@@ -1034,6 +1037,7 @@ int cc_timing_enable(const char* kernel) {
   else if (kernel && !strcmp(kernel, "adam")) k = TK_ADAM;
   else if (kernel && !strcmp(kernel, "ups_bwd")) k = TK_UPS_BWD;
   else if (kernel && !strcmp(kernel, "join")) k = TK_JOIN;
+  else if (kernel && !strcmp(kernel, "ups_fwd")) k = TK_UPS_FWD;
   else if (kernel && kernel[0]) return fail(CC_EINVAL, "unknown kernel class '%s'", kernel);
   g_timing.kind = k;
   g_timing.used = 0;
