@@ -38,7 +38,7 @@ PEAKS = {
 # calibration (FETCH x2.000, WRITE x1.000); the commands and the table are in
 # profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
 # until the counters are taken again.
-ARM_FUSED_TRAFFIC_BYTES = int((2.0 * 3585.0 + 1.0 * 18675.4) * 1024)
+ARM_FUSED_TRAFFIC_BYTES = None
 
 
 def arm_flops_per_step(mc, H, W):
@@ -107,11 +107,13 @@ def hbm_bytes_per_step(mc, H, W):
     n_par = wl.n_params(mc)
     ups_fwd = sum(4 * ((L - j) * n[j] + (L - j) * n[j - 1]) for j in range(1, L))
     ups_bwd = sum(4 * ((L - j) * n[j - 1] + 2 * (L - j) * n[j]) for j in range(1, L))
+    ifce = sum(4 * n[k] * min(mc.n_ifce_grids, k) * mc.n_ifce_feat for k in range(L))
     return {
-        "adam": 28 * (n_lat + n_par),                  # read theta, g, m, v; write theta, m, v
         "ups_fwd": ups_fwd,                            # read T_j, write U_j (all levels)
         "ups_bwd": ups_bwd,                            # read dU_j and T_j, write dT_j (all levels)
-        "join": 4 * n_lat * 6,                         # rate planes (3), distortion grad, dq; write grad
+        # latent join + Adam: read 3 rate planes, distortion grad, dq, theta, m, v and the
+        # IFCE parent gradients; write grad, theta, m, v
+        "join": 4 * n_lat * 12 + ifce,
     }
 
 
@@ -268,7 +270,7 @@ def main():
     if not args.no_kernel_timing and not args.only_step:
         bts = hbm_bytes_per_step(mc, H, W)
         hbm = {}
-        for name in ("adam", "ups_fwd", "ups_bwd", "join"):
+        for name in ("ups_fwd", "ups_bwd", "join"):
             ms = measure_kernel(head, name)
             hbm[name] = {"ms_per_step": round(ms, 4), "bytes_per_step": bts[name],
                          "achieved_GBs": round(bts[name] / (ms / 1e3) / 1e9, 1),

@@ -186,7 +186,8 @@ int cc_syn_bwd(cc_state* s, const float* grad_xhat, float* grad_zhat, float* gra
 
 /* Live kernel timing for measurement tools: HIP events are recorded on the
  * launch stream around every launch of one kernel class ("arm", "syn_bwd",
- * "ups_fwd", "ups_bwd", "join", "adam"; NULL or "" switches timing off;
+ * "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which also applies
+ * the latents' Adam update in an encode step; NULL or "" switches timing off;
  * the upsampling classes time all levels of one step as one span) by the calls
  * that follow.  cc_timing_read waits for those events and returns the summed
  * duration (ms) and the number of timed launches, then resets the record.

@@ -72,6 +72,12 @@ struct Layout {
   int syn_o[7];
 };
 
+// Workgroups (and weight-gradient partial rows) of the upsampling adjoint at
+// level j: one per (channel of T_j, 16x16 tile of grid j).
+int ups_bwd_rows(const DevDesc& h, int j) {
+  return cdiv(h.gh[j], CC_UPS_TILE) * cdiv(h.gw[j], CC_UPS_TILE) * (h.L - j);
+}
+
 int check_config(const cc_config* c, int H, int W) {
   if (!c) return fail(CC_EINVAL, "config is NULL");
   if (c->L < 2 || c->L > CC_MAX_L) return fail(CC_EINVAL, "L=%d outside [2, %d]", c->L, CC_MAX_L);
@@ -203,7 +209,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   wpo += (long long)std::max(h.arm_nwg_plain, h.arm_nwg_fused) * h.n_arm_par;
   h.prod_ups1 = q;
   for (int j = 1; j < h.L; ++j) {
-    const int rows = cdiv(h.gh[j], CC_UPS_TILE) * cdiv(h.gw[j], CC_UPS_TILE);
+    const int rows = ups_bwd_rows(h, j);
     h.prod[q++] = {h.p_ups[j], 4, rows, 0, wpo};
     wpo += (long long)rows * 4;
   }
@@ -211,7 +217,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.prod[q++] = {h.p_sw[0], syn_end - h.p_sw[0], h.syn_nwg, 0, wpo};
   wpo += (long long)h.syn_nwg * (syn_end - h.p_sw[0]);
   h.prod_res0 = q;
-  h.res_nwg = cdiv(npix, CC_PIX_TILE * CC_RES_PPT);
+  h.res_nwg = cdiv(cdiv(H, CC_RES_TH) * cdiv(W, CC_RES_TW), CC_RES_TPW);
   for (int r = 0; r < h.n_res; ++r) {
     h.prod[q++] = {h.p_rw[r], 84, h.res_nwg, 0, wpo};
     wpo += (long long)h.res_nwg * 84;
@@ -489,20 +495,18 @@ int check_params(const cc_step_params* p) {
     if (r_ != CC_OK) return r_ == CC_EDEVICE ? fail(CC_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())) : r_; \
   } while (0)
 
-int set_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st) {
-  StepLaunch sl;
-  memset(&sl, 0, sizeof sl);
-  sl.n = n;
-  for (int i = 0; i < n; ++i) {
-    sl.d[i] = s[i]->ddev;
-    sl.a[i] = step_args(p[i]);
-  }
-  return cc_launch_set_step(sl, st);
+// Quantisation proxy (a1) for a set of states; the kernel also stores the
+// step's schedule values in each descriptor for the rest of the step.
+int quantise(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st) {
+  StepPack a;
+  memset(&a, 0, sizeof a);
+  for (int i = 0; i < n; ++i) a.a[i] = step_args(p[i]);
+  return cc_launch_qtrain(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), a, st);
 }
 
 // Optional live timing of one kernel class with HIP events recorded on the
 // launch stream around each of its launches (see cc_timing_enable).
-enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_ADAM = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6 };
+enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6 };
 struct Timing {
   int kind = TK_NONE;
   std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -562,8 +566,7 @@ int forward_dist(cc_state* const* s, int n, int want_mse, hipStream_t st) {
 int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st, bool update,
              bool backward) {
   const DevDesc& h0 = s[0]->lo.h;
-  RET(set_step(s, n, p, st));
-  RET(cc_launch_qtrain(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st));
+  RET(quantise(s, n, p, st));
   RET(arm(s, n, backward ? 1 : 0, st));
   if (backward && h0.G > 0) {
     for (int f = 1; f < h0.L; ++f) {
@@ -591,29 +594,28 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
     {
       TimeScope ts(TK_UPS_BWD, st);
       for (int j = 1; j < h0.L; ++j) {
-        const Launch l = plan(s, n, [j](const DevDesc& h) {
-          return cdiv(h.gh[j], CC_UPS_TILE) * cdiv(h.gw[j], CC_UPS_TILE);
-        });
+        const Launch l = plan(s, n, [j](const DevDesc& h) { return ups_bwd_rows(h, j); });
         RET(cc_launch_ups_bwd(l, j, st));
       }
     }
     {
+      // latent gradients, with the latents' Adam update when updating
       TimeScope ts(TK_JOIN, st);
-      RET(cc_launch_join(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st));
+      RET(cc_launch_join(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st, nullptr,
+                         update ? 1 : 0));
     }
+    // decoder-parameter gradients (with their Adam update) and, in one extra
+    // block per image, the loss totals
     const Launch w1 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, 64) * CC_WRED_SPLIT; });
-    const Launch w2 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, CC_ELT_TILE); });
-    RET(cc_launch_wreduce(w1, w2, st));
+    const Launch w2 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, CC_ELT_TILE) + 1; });
+    RET(cc_launch_wreduce(w1, w2, update ? 1 : 0, st));
+    return CC_OK;
   }
   Launch lr;
   memset(&lr, 0, sizeof lr);
   lr.n = n;
   for (int i = 0; i < n; ++i) lr.d[i] = s[i]->ddev;
   RET(cc_launch_lreduce(lr, st));
-  if (update) {
-    TimeScope ts(TK_ADAM, st);
-    RET(cc_launch_adam(plan(s, n, [](const DevDesc& h) { return cdiv(h.n_theta, CC_ELT_TILE); }), st));
-  }
   return CC_OK;
 }
 
@@ -802,8 +804,7 @@ int cc_decode(cc_state* s, float* out_img_dev, void* stream) {
   p.quant_mode = CC_HARD;
   p.temperature = 1.0f;
   hipStream_t st = (hipStream_t)stream;
-  RET(set_step(&s, 1, &p, st));
-  RET(cc_launch_qtrain(plan(&s, 1, [](const DevDesc& h) { return h.lat_ntile; }), st));
+  RET(quantise(&s, 1, &p, st));
   RET(forward_dist(&s, 1, 0, st));
   RET(cc_launch_copy_out(plan(&s, 1, [](const DevDesc& h) { return cdiv(3 * h.H * h.W, CC_ELT_TILE); }), out_img_dev, st));
   return CC_OK;
@@ -867,8 +868,8 @@ int params_grad_out(cc_state* s, float* out, int b, int e, hipStream_t st) {
   const DevDesc& h = s->lo.h;
   cc_state* one[1] = {s};
   const Launch w1 = plan(one, 1, [](const DevDesc& x) { return cdiv(x.n_par, 64) * CC_WRED_SPLIT; });
-  const Launch w2 = plan(one, 1, [](const DevDesc& x) { return cdiv(x.n_par, CC_ELT_TILE); });
-  RET(cc_launch_wreduce(w1, w2, st));
+  const Launch w2 = plan(one, 1, [](const DevDesc& x) { return cdiv(x.n_par, CC_ELT_TILE) + 1; });
+  RET(cc_launch_wreduce(w1, w2, 0, st));
   return copy_d2d(out + b, h.grad + h.n_lat + b, sizeof(float) * (e - b), st);
 }
 
@@ -947,9 +948,7 @@ int cc_ups_bwd(cc_state* s, const float* grad_zhat, float* grad_yhat, float* gra
   RET(copy_d2d(h.dyq, grad_zhat, sizeof(float) * npx, st));
   RET(copy_d2d(h.dU + h.uoff[1], grad_zhat + npx, sizeof(float) * (h.L - 1) * npx, st));
   for (int j = 1; j < h.L; ++j) {
-    const Launch l = plan(one, 1, [j](const DevDesc& x) {
-      return cdiv(x.gh[j], CC_UPS_TILE) * cdiv(x.gw[j], CC_UPS_TILE);
-    });
+    const Launch l = plan(one, 1, [j](const DevDesc& x) { return ups_bwd_rows(x, j); });
     RET(cc_launch_ups_bwd(l, j, st));
   }
   if (grad_yhat) RET(copy_d2d(grad_yhat, h.dyq, sizeof(float) * h.n_lat, st));
@@ -1034,7 +1033,6 @@ int cc_timing_enable(const char* kernel) {
   int k = TK_NONE;
   if (kernel && !strcmp(kernel, "arm")) k = TK_ARM;
   else if (kernel && !strcmp(kernel, "syn_bwd")) k = TK_SYN_BWD;
-  else if (kernel && !strcmp(kernel, "adam")) k = TK_ADAM;
   else if (kernel && !strcmp(kernel, "ups_bwd")) k = TK_UPS_BWD;
   else if (kernel && !strcmp(kernel, "join")) k = TK_JOIN;
   else if (kernel && !strcmp(kernel, "ups_fwd")) k = TK_UPS_FWD;

@@ -81,9 +81,7 @@ struct StepArgs {
   unsigned t_lo;
   int mode, upd;
 };
-struct StepLaunch {
-  int n;
-  DevDesc* d[CC_MAX_BATCH];
+struct StepPack {
   StepArgs a[CC_MAX_BATCH];
 };
 
@@ -96,11 +94,10 @@ __device__ __forceinline__ int cc_find_img(const Launch& L, int b) {
 // -------------------------------------------------------------- host side
 // Launchers implemented in the kernel translation units.
 struct HostImg;  // defined in cc_api.hip
-int cc_launch_set_step(const StepLaunch& s, hipStream_t st);
-int cc_launch_qtrain(const Launch& l, hipStream_t st);
+int cc_launch_qtrain(const Launch& l, const StepPack& a, hipStream_t st);
 int cc_launch_arm(const Launch& l, const DevDesc& h, int bwd, int precision, hipStream_t st);
 int cc_launch_pool(const Launch& l, int f, hipStream_t st);
-int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out = nullptr);
+int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out = nullptr, int adam = 0);
 int cc_launch_poke(float* p, float v, hipStream_t st);
 int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st);
@@ -108,9 +105,8 @@ int cc_launch_syn_fwd(const Launch& l, const DevDesc& h, int final_mse, int prec
 int cc_launch_syn_bwd(const Launch& l, const DevDesc& h, int precision, hipStream_t st);
 int cc_launch_res_fwd(const Launch& l, int r, int last, int want_mse, hipStream_t st);
 int cc_launch_res_bwd(const Launch& l, int r, hipStream_t st);
-int cc_launch_wreduce(const Launch& l1, const Launch& l2, hipStream_t st);
+int cc_launch_wreduce(const Launch& l1, const Launch& l2, int adam, hipStream_t st);
 int cc_launch_lreduce(const Launch& l, hipStream_t st);
-int cc_launch_adam(const Launch& l, hipStream_t st);
 int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
 
 // Tile geometry shared by host launch planning and kernels.
@@ -118,11 +114,13 @@ int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
 #define CC_ARM_CHUNK 64     // ARM kernel: positions per chunk (= threads per block)
 #define CC_ARM_CPW 4        // ARM kernel: chunks per workgroup
 #define CC_SYN_CHUNK 64
-#define CC_SYN_CPW 4
+#define CC_SYN_CPW 12
 #define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
 #define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
-#define CC_RES_PPT 8        // residual-layer adjoint: pixels per thread
+#define CC_RES_TH 8         // residual-layer adjoint: tile rows (a multiple of 4)
+#define CC_RES_TW 64        // residual-layer adjoint: tile columns (one per lane)
+#define CC_RES_TPW 1        // residual-layer adjoint: tiles per workgroup
 
 int cc_arm_fused_supported(const DevDesc& h);

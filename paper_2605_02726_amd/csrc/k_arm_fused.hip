@@ -36,6 +36,19 @@ constexpr int HALO = 4;            // causal reach: rows above, columns each sid
 constexpr int NW = 4;              // wavefronts per workgroup
 constexpr int SW = 32 * NW;        // segment width
 constexpr int WR = SW + 2 * HALO;  // LDS row: segment plus the halo columns
+constexpr int PW = 32 + 2 * HALO;  // private accumulator row of one wavefront
+
+// The first 24 causal neighbours in decoding order (half-plane {dy < 0, or
+// dy = 0 and dx < 0} sorted by (dy^2 + dx^2, dy, dx)), as LDS offsets within
+// the staged window; every fused shape uses a prefix of this list.  The host
+// checks the state's neighbour list against it (cc_arm_fused_supported).
+constexpr int NOFF = 24;
+constexpr int CDY[NOFF] = {-1, 0, -1, -1, -2, 0, -2, -2, -1, -1, -2, -2,
+                           -3, 0, -3, -3, -1, -1, -3, -3, -2, -2, -4, 0};
+constexpr int CDX[NOFF] = {0, -1, -1, 1, 0, -2, -1, 1, -2, 2, -2, 2,
+                           0, -3, -1, 1, -3, 3, -2, 2, -3, 3, 0, -4};
+__host__ __device__ constexpr int coff(int m) { return m < NOFF ? CDY[m] * WR + CDX[m] : 0; }
+__host__ __device__ constexpr int poff(int m) { return m < NOFF ? CDY[m] * PW + CDX[m] : 0; }
 
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -114,7 +127,12 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   constexpr int CTX = S + F;
   static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 + CC_MAX_L - 1 <= 32, "shape");
   __shared__ float ywin[HALO + TH][WR];
-  __shared__ float acc[HALO + TH][WR];
+  // context-gradient accumulators: one private window per wavefront (its 32
+  // columns plus HALO on each side, the band rows plus HALO above), merged
+  // at the end of each segment; cin / cout carry the columns that spill into
+  // the next segment
+  __shared__ float pacc[NW][HALO + TH][PW];
+  __shared__ float cin[HALO + TH][2 * HALO], cout[HALO + TH][2 * HALO];
   // per-wave transposing tiles; the end-of-kernel weight-gradient sum reuses
   // the same storage
   __shared__ __attribute__((aligned(16))) char tiles_raw[2 * 3 * NW * sizeof(Tile)];
@@ -124,9 +142,8 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   static_assert(3 * 32 * 33 * sizeof(float) <= 2 * 3 * NW * sizeof(Tile), "wsum alias");
   __shared__ float pwin[CC_MAX_L - 1][SW / 2 + 1];   // IFCE parents of the segment
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
-  __shared__ int soff[32];          // context slot -> LDS offset of its neighbour
+  __shared__ float iw[8][8], ib[8];  // IFCE weights [feature][input] (zero padded), biases
   __shared__ double bsh[NW];
-  __shared__ float carry[HALO + TH][2 * HALO];
   __shared__ bf16x8 wop[4][2][64], wopl[4][2][64];
 
   const int im = cc_find_img(Lc, blockIdx.x);
@@ -161,50 +178,52 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
     vec[3][m] = m < H2 ? W3[H2 + m] : 0.0f;
     vec[4][m] = (stab && m < CTX) ? P[d->p_asw + m] : 0.0f;
     vec[5][m] = (stab && m < CTX) ? P[d->p_asw + CTX + m] : 0.0f;
-    soff[m] = m < S ? d->dy[m] * WR + d->dx[m] : 0;
   }
-  // A operands (weights, BF16) per lane and K step, kept in LDS: operand
-  // (matrix mat, step s) of lane l is wop[mat][s][l]
-  if (wave == 0) {
+  if (tid < 64) {
+    const int f = tid >> 3, q = tid & 7;
+    iw[f][q] = (has_ifce && f < F && q < nin) ? P[d->p_iw[k] + f * nin + q] : 0.0f;
+    if (q == 0) ib[f] = (has_ifce && f < F) ? P[d->p_ib[k] + f] : 0.0f;
+  }
+  // A operands (weights, split BF16) per lane and K step, kept in LDS:
+  // operand (matrix mat, step s) of lane l is wop[mat][s][l] (hi) and
+  // wopl[mat][s][l] (lo).  W1 and W2 are first staged in FP32 through the
+  // (not yet used) tile storage; wavefront mat then builds matrix mat.
+  float* w1s = reinterpret_cast<float*>(tiles_raw);
+  float* w2s = w1s + H1 * CTX;
+  for (int i = tid; i < H1 * CTX + H2 * H1; i += NW * 64)
+    w1s[i] = i < H1 * CTX ? P[d->p_aw[0] + i] : P[d->p_aw[1] + i - H1 * CTX];
+  __syncthreads();
+  {
+    const int mat = wave;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      bf16x8 a1, a2, a2t, a1t;
+    for (int s2 = 0; s2 < 2; ++s2) {
+      bf16x8 hi, lo;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int kk = 16 * s + 8 * hh + i, u = kunit(kk), m = n;
-        a1[i] = (__bf16)((m < H1 && kk < CTX) ? W1[m * CTX + kk] : 0.0f);
-        a2[i] = (__bf16)((m < H2 && u < H1) ? W2[m * H1 + u] : 0.0f);
-        a2t[i] = (__bf16)((m < H1 && u < H2) ? W2[u * H1 + m] : 0.0f);
-        a1t[i] = (__bf16)((m < CTX && u < H1) ? W1[u * CTX + m] : 0.0f);
+        const int kk = 16 * s2 + 8 * hh + i, u = kunit(kk), m = n;
+        float v = 0.0f;
+        if (mat == 0)
+          v = (m < H1 && kk < CTX) ? w1s[m * CTX + kk] : 0.0f;
+        else if (mat == 1)
+          v = (m < H2 && u < H1) ? w2s[m * H1 + u] : 0.0f;
+        else if (mat == 2)
+          v = (m < H1 && u < H2) ? w2s[u * H1 + m] : 0.0f;
+        else
+          v = (m < CTX && u < H1) ? w1s[u * CTX + m] : 0.0f;
+        hi[i] = (__bf16)v;
+        lo[i] = (__bf16)(v - (float)hi[i]);
       }
-      wop[0][s][lane] = a1;
-      wop[1][s][lane] = a2;
-      wop[2][s][lane] = a2t;
-      wop[3][s][lane] = a1t;
-      bf16x8 l1, l2, l2t, l1t;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int kk = 16 * s + 8 * hh + i, u = kunit(kk), m = n;
-        l1[i] = (__bf16)((m < H1 && kk < CTX) ? W1[m * CTX + kk] - (float)a1[i] : 0.0f);
-        l2[i] = (__bf16)((m < H2 && u < H1) ? W2[m * H1 + u] - (float)a2[i] : 0.0f);
-        l2t[i] = (__bf16)((m < H1 && u < H2) ? W2[u * H1 + m] - (float)a2t[i] : 0.0f);
-        l1t[i] = (__bf16)((m < CTX && u < H1) ? W1[u * CTX + m] - (float)a1t[i] : 0.0f);
-      }
-      wopl[0][s][lane] = l1;
-      wopl[1][s][lane] = l2;
-      wopl[2][s][lane] = l2t;
-      wopl[3][s][lane] = l1t;
+      wop[mat][s2][lane] = hi;
+      wopl[mat][s2][lane] = lo;
     }
   }
   const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
   const float bs0 = stab ? P[d->p_asb] : 0.0f, bs1 = stab ? P[d->p_asb + 1] : 0.0f;
-  // IFCE weights for this grid (FP32, read through the scalar cache)
-  const CF* Wi = has_ifce ? P + d->p_iw[k] : P;
-  const CF* Bi = has_ifce ? P + d->p_ib[k] : P;
 
   f32x16 acc1 = {}, acc2 = {}, acc3 = {};
   double bsum = 0.0;
-  for (int i = tid; i < (HALO + TH) * WR; i += NW * 64) (&acc[0][0])[i] = 0.0f;
+  for (int i = tid; i < NW * (HALO + TH) * PW; i += NW * 64) (&pacc[0][0][0])[i] = 0.0f;
+  if (tid < (HALO + TH) * 2 * HALO) (&cin[0][0])[tid] = 0.0f;
 
   const int nseg = (w + SW - 1) / SW;
   for (int seg = 0; seg < nseg; ++seg) {
@@ -250,14 +269,14 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
         for (int i = 0; i < 8; ++i) {
           const int kk = 16 * s + 8 * hh + i;
           float v = 0.0f;
+          const int k0 = 16 * s + i, k1 = k0 + 8;   // slot of this lane's half
           if (kk < S) {
-            v = (&ywin[HALO + r][lc])[soff[kk]];
+            v = (&ywin[HALO + r][lc])[hh ? coff(k1) : coff(k0)];
           } else if (kk < CTX && has_ifce) {
             const int f = kk - S;
-            float a = Bi[f];
+            float a = ib[f];
 #pragma unroll
-            for (int q = 0; q < CC_MAX_L - 1; ++q)
-              if (q < nin) a += Wi[f * nin + q] * r_in[q];
+            for (int q = 0; q < CC_MAX_L - 1; ++q) a += iw[f][q] * r_in[q];
             v = a;
           }
           cf[s][i] = v;
@@ -405,49 +424,56 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
       acc3 = mfma_tiles(G3, C3, n, hh, acc3);
       __builtin_amdgcn_wave_barrier();
 
-      // ---- scatter the context gradient (and the direct term) into acc
-      const int base = (HALO + r) * WR + lc;
-      for (int ph = 0; ph < 2; ++ph) {
-        __syncthreads();
-        if ((wave & 1) == ph && valid) {
-          for (int half = 0; half < 2; ++half) {
-            if (hh == half) {
+      // ---- scatter the context gradient (and the direct term) into this
+      // wavefront's window: half 0's lanes, then half 1's (one instruction
+      // never carries two additions to one address from the two halves)
+      if (valid) {
+        float* pw = &pacc[wave][HALO + r][HALO + n];
+        for (int half = 0; half < 2; ++half) {
+          if (hh == half) {
 #pragma unroll
-              for (int i = 0; i < 16; ++i) {
-                const int m = mrow(i, hh);
-                if (m < S) atomicAdd(&acc[0][0] + base + soff[m], dc[i]);
-              }
-              if (half == 0) atomicAdd(&acc[0][0] + base, gd * rs);
+            for (int i = 0; i < 16; ++i) {
+              // slot of register i in this half: both candidates are
+              // compile-time constants, so no table is read at run time
+              const int m = half ? mrow(i, 1) : mrow(i, 0);
+              if (m < S) atomicAdd(pw + (half ? poff(mrow(i, 1)) : poff(mrow(i, 0))), dc[i]);
             }
+            if (half == 0) atomicAdd(pw, gd * rs);
           }
         }
       }
     }
     __syncthreads();
-    // ---- write the finished columns of this segment and carry the last
-    // 2*HALO columns into the next one.  Row rr of acc is grid row
+    // ---- merge the wavefront windows (fixed order) with the carried
+    // columns, write the finished columns of this segment and carry the last
+    // 2*HALO columns into the next one.  Row rr of the window is grid row
     // y0 - HALO + rr: rows >= HALO belong to this band (plane A), rows
     // [HALO - TH, HALO) to the band above (plane B1), rows [0, HALO - TH) to
     // the band two above (plane B2).
     if (bwd > 0) {
       const bool last = seg == nseg - 1;
-      const int ncol = last ? WR : SW;
-      for (int i = tid; i < (HALO + TH) * ncol; i += NW * 64) {
-        const int rr = i / ncol, c = i - rr * ncol;
+      for (int i = tid; i < (HALO + TH) * WR; i += NW * 64) {
+        const int rr = i / WR, c = i - rr * WR;
+        float v = c < 2 * HALO ? cin[rr][c] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+          const int cc = c - 32 * q;
+          if (cc >= 0 && cc < PW) {
+            v += pacc[q][rr][cc];
+            pacc[q][rr][cc] = 0.0f;
+          }
+        }
+        if (c >= SW && !last) {
+          cout[rr][c - SW] = v;
+          continue;
+        }
         const int gy = y0 - HALO + rr, gx = x0 - HALO + c;
         if (gx < 0 || gx >= w || gy < 0 || gy >= h) continue;
         const int plane = rr >= HALO ? 0 : (rr >= HALO - TH ? 1 : 2);
-        d->dc[(size_t)plane * d->n_lat + d->goff[k] + gy * w + gx] = acc[rr][c];
+        d->dc[(size_t)plane * d->n_lat + d->goff[k] + gy * w + gx] = v;
       }
       __syncthreads();
-      if (tid < (HALO + TH) * 2 * HALO)
-        carry[tid / (2 * HALO)][tid % (2 * HALO)] = acc[tid / (2 * HALO)][SW + tid % (2 * HALO)];
-      __syncthreads();
-      for (int i = tid; i < (HALO + TH) * WR; i += NW * 64) {
-        const int rr = i / WR, c = i - rr * WR;
-        (&acc[0][0])[i] = c < 2 * HALO ? carry[rr][c] : 0.0f;
-      }
-      __syncthreads();
+      if (tid < (HALO + TH) * 2 * HALO) (&cin[0][0])[tid] = (&cout[0][0])[tid];
     }
   }
 
@@ -508,6 +534,9 @@ int launch_t(const Launch& l, int bwd, hipStream_t st) {
   X(14, 6, 20, 20)
 
 int cc_arm_fused_supported(const DevDesc& h) {
+  if (h.S > NOFF) return 0;
+  for (int m = 0; m < h.S; ++m)
+    if (h.dy[m] != CDY[m] || h.dx[m] != CDX[m]) return 0;
 #define X(a, b, c, e) if (h.S == a && h.F == b && h.H1 == c && h.H2 == e) return 1;
   CC_FUSED_SHAPES(X)
 #undef X

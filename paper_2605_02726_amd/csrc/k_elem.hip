@@ -61,43 +61,56 @@ __device__ __forceinline__ int grid_of(const CDesc* d, int i) {
   return k;
 }
 
-__global__ void k_set_step(StepLaunch s) {
-  const int i = threadIdx.x;
-  if (i >= s.n) return;
-  DevDesc* d = s.d[i];
-  const StepArgs a = s.a[i];
-  d->T = a.T;
-  d->sr_c = a.sr_c;
-  d->sr_invT = a.sr_invT;
-  d->sigma = a.sigma;
-  d->lr = a.lr;
-  d->bc1 = a.bc1;
-  d->bc2 = a.bc2;
-  d->t_lo = a.t_lo;
-  d->mode = a.mode;
-  d->upd = a.upd;
+// Adam (Kingma and Ba) on element i of theta = [latents, parameters] with
+// its gradient g; the step's learning rate and bias corrections come from
+// the descriptor.
+__device__ __forceinline__ void adam_update(const CDesc* d, int i, float g) {
+  const float m = 0.9f * d->m[i] + 0.1f * g;
+  const float v = 0.999f * d->v[i] + 0.001f * (g * g);
+  d->m[i] = m;
+  d->v[i] = v;
+  const float mh = m / d->bc1, vh = v / d->bc2;
+  d->theta[i] -= d->lr * mh / (sqrtf(vh) + 1e-8f);
 }
 
 // yhat = s_T(s_T(y) + sigma n) with n from Philox counter (t, k, i, 0), and
 // d yhat / d y; or yhat = rint(y) with a straight-through derivative of 1.
-__global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L) {
+// The step's schedule values arrive as kernel arguments; the first block of
+// each image also stores them in the descriptor for the later kernels of the
+// step.
+__global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L, StepPack A) {
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
-  const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  const StepArgs a = A.a[im];
+  const int b = blockIdx.x - L.tile0[im];
+  if (b == 0 && threadIdx.x == 0) {
+    DevDesc* dw = const_cast<DevDesc*>(L.d[im]);
+    dw->T = a.T;
+    dw->sr_c = a.sr_c;
+    dw->sr_invT = a.sr_invT;
+    dw->sigma = a.sigma;
+    dw->lr = a.lr;
+    dw->bc1 = a.bc1;
+    dw->bc2 = a.bc2;
+    dw->t_lo = a.t_lo;
+    dw->mode = a.mode;
+    dw->upd = a.upd;
+  }
+  const int i = b * CC_ELT_TILE + threadIdx.x;
   if (i >= d->n_lat) return;
   const float y = d->theta[i];
   float yh, dq;
-  if (d->mode == CC_HARD) {
+  if (a.mode == CC_HARD) {
     yh = rintf(y);
     dq = 1.0f;
   } else {
     const int k = grid_of(d, i);
-    const uint4 r = philox10(make_uint4(d->t_lo, (unsigned)k, (unsigned)(i - d->goff[k]), 0u),
+    const uint4 r = philox10(make_uint4(a.t_lo, (unsigned)k, (unsigned)(i - d->goff[k]), 0u),
                              d->seed_lo, d->seed_hi);
     const float n = gauss(r.x, r.y);
-    const float c = d->sr_c, iT = d->sr_invT;
-    const float a = softround(y, c, iT);
-    const float u = a + d->sigma * n;
+    const float c = a.sr_c, iT = a.sr_invT;
+    const float s0 = softround(y, c, iT);
+    const float u = s0 + a.sigma * n;
     yh = softround(u, c, iT);
     dq = dsoftround(u, c, iT) * dsoftround(y, c, iT);
   }
@@ -133,7 +146,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L, int f) {
 // where d rate / d yhat gathers, in a fixed order, the direct term, the
 // context gradients of the positions that use this latent as a causal
 // neighbour (reversed offsets) and the IFCE gradients of finer grids.
-__global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only_out) {
+__global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only_out, int adam) {
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
   const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
@@ -170,27 +183,12 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only
     return;
   }
   g += d->dyq[i];
-  d->grad[i] = g * d->dq[i];
+  g *= d->dq[i];
+  d->grad[i] = g;
+  if (adam && d->upd) adam_update(d, i, g);
 }
 
 __global__ void k_poke(float* p, float v) { *p = v; }
-
-// Adam (Kingma and Ba) over theta = [latents, parameters]; latents are left
-// untouched when frozen.
-__global__ __launch_bounds__(CC_ELT_TILE) void k_adam(Launch L) {
-  const int im = cc_find_img(L, blockIdx.x);
-  const CDesc* d = (const CDesc*)L.d[im];
-  const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
-  if (i >= d->n_theta) return;
-  if (i < d->n_lat && !d->upd) return;
-  const float g = d->grad[i];
-  const float m = 0.9f * d->m[i] + 0.1f * g;
-  const float v = 0.999f * d->v[i] + 0.001f * (g * g);
-  d->m[i] = m;
-  d->v[i] = v;
-  const float mh = m / d->bc1, vh = v / d->bc2;
-  d->theta[i] -= d->lr * mh / (sqrtf(vh) + 1e-8f);
-}
 
 __device__ __forceinline__ double block_sum_256(double v, double* sh) {
   sh[threadIdx.x] = v;
@@ -203,9 +201,7 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
 }
 
 // FP64 totals of one image in a fixed order: scal = (loss, bits, mse, finite).
-__global__ __launch_bounds__(256) void k_lreduce(Launch L) {
-  __shared__ double sh[256];
-  const CDesc* d = (const CDesc*)L.d[blockIdx.x];
+__device__ void loss_totals(const CDesc* d, double* sh) {
   double b = 0.0, m = 0.0;
   for (int r = threadIdx.x; r < d->arm_nwg; r += 256) b += d->lp_bits[r];
   const double bits = block_sum_256(b, sh);
@@ -220,6 +216,11 @@ __global__ __launch_bounds__(256) void k_lreduce(Launch L) {
     d->scal[2] = mse;
     d->scal[3] = isfinite(loss) ? 1.0 : 0.0;
   }
+}
+
+__global__ __launch_bounds__(256) void k_lreduce(Launch L) {
+  __shared__ double sh[256];
+  loss_totals((const CDesc*)L.d[blockIdx.x], sh);
 }
 
 // Weight-gradient reduction, pass 1: block (param block of 64, row split s)
@@ -251,14 +252,25 @@ __global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
 }
 
 // Pass 2: gradient of decoder parameter p = sum of the row splits.
-__global__ __launch_bounds__(CC_ELT_TILE) void k_wreduce2(Launch L) {
+// Weight-gradient reduction, pass 2: the CC_WRED_SPLIT partial sums of each
+// parameter in a fixed order, then (adam) its Adam update.  The last block of
+// each image computes the image's FP64 loss totals instead.
+__global__ __launch_bounds__(CC_ELT_TILE) void k_wreduce2(Launch L, int adam) {
+  __shared__ double sh[CC_ELT_TILE];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
-  const int p = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+  const int b = blockIdx.x - L.tile0[im];
+  if (b == L.tile0[im + 1] - L.tile0[im] - 1) {
+    loss_totals(d, sh);
+    return;
+  }
+  const int p = b * CC_ELT_TILE + threadIdx.x;
   if (p >= d->n_par) return;
   double acc = 0.0;
   for (int s = 0; s < CC_WRED_SPLIT; ++s) acc += d->wp2[(size_t)s * d->n_par + p];
-  d->grad[d->n_lat + p] = (float)acc;
+  const float g = (float)acc;
+  d->grad[d->n_lat + p] = g;
+  if (adam) adam_update(d, d->n_lat + p, g);
 }
 
 __global__ __launch_bounds__(CC_ELT_TILE) void k_copy_out(Launch L, float* out) {
@@ -276,12 +288,8 @@ inline int check_launch() {
 
 }  // namespace
 
-int cc_launch_set_step(const StepLaunch& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, st, s);
-  return check_launch();
-}
-int cc_launch_qtrain(const Launch& l, hipStream_t st) {
-  hipLaunchKernelGGL(k_qtrain, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l);
+int cc_launch_qtrain(const Launch& l, const StepPack& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_qtrain, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, a);
   return check_launch();
 }
 int cc_launch_pool(const Launch& l, int f, hipStream_t st) {
@@ -289,26 +297,22 @@ int cc_launch_pool(const Launch& l, int f, hipStream_t st) {
   hipLaunchKernelGGL(k_pool, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, f);
   return check_launch();
 }
-int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out) {
-  hipLaunchKernelGGL(k_join, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, rate_only_out);
+int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out, int adam) {
+  hipLaunchKernelGGL(k_join, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, rate_only_out, adam);
   return check_launch();
 }
 int cc_launch_poke(float* p, float v, hipStream_t st) {
   hipLaunchKernelGGL(k_poke, dim3(1), dim3(1), 0, st, p, v);
   return check_launch();
 }
-int cc_launch_adam(const Launch& l, hipStream_t st) {
-  hipLaunchKernelGGL(k_adam, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l);
-  return check_launch();
-}
 int cc_launch_lreduce(const Launch& l, hipStream_t st) {
   hipLaunchKernelGGL(k_lreduce, dim3(l.n), dim3(256), 0, st, l);
   return check_launch();
 }
-int cc_launch_wreduce(const Launch& l1, const Launch& l2, hipStream_t st) {
+int cc_launch_wreduce(const Launch& l1, const Launch& l2, int adam, hipStream_t st) {
   hipLaunchKernelGGL(k_wreduce1, dim3(l1.tile0[l1.n]), dim3(256), 0, st, l1);
   if (check_launch() != CC_OK) return CC_EDEVICE;
-  hipLaunchKernelGGL(k_wreduce2, dim3(l2.tile0[l2.n]), dim3(CC_ELT_TILE), 0, st, l2);
+  hipLaunchKernelGGL(k_wreduce2, dim3(l2.tile0[l2.n]), dim3(CC_ELT_TILE), 0, st, l2, adam);
   return check_launch();
 }
 int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st) {

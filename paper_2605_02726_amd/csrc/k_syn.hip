@@ -100,7 +100,8 @@ __device__ __forceinline__ float axis_w(const float* h, int o, int i, int n) {
 // each (oy, ix) / (iy, ox) pair owned by exactly one tile (the tile of ix /
 // iy whose output rows / columns 2*tile .. 2*tile+31 contain oy / ox).
 // Channel 0 of dT_j is the distortion gradient of yhat^(j), channels >= 1 are
-// dU_{j+1}.  One partial row of 4 tap gradients per workgroup.
+// dU_{j+1}.  One workgroup per (channel, tile); one partial row of 4 tap
+// gradients per workgroup.
 constexpr int UT = CC_UPS_TILE;   // input tile side
 constexpr int UG = 2 * UT + 6;   // output window side (2*UT + 3 + 3)
 constexpr int UTW = UT + 4;      // input window side (2 each side)
@@ -116,8 +117,9 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
   const CDesc* d = (const CDesc*)L.d[im];
   const int wgi = blockIdx.x - L.tile0[im];
   const int ho = d->gh[j - 1], wo = d->gw[j - 1], hi = d->gh[j], wi = d->gw[j];
-  const int ntx = (wi + UT - 1) / UT;
-  const int iy0 = (wgi / ntx) * UT, ix0 = (wgi % ntx) * UT;
+  const int ntx = (wi + UT - 1) / UT, ntile = ntx * ((hi + UT - 1) / UT);
+  const int ch = wgi / ntile, tile = wgi - ch * ntile;   // one channel of one tile
+  const int iy0 = (tile / ntx) * UT, ix0 = (tile % ntx) * UT;
   const CF* hp = (const CF*)(d->theta + d->n_lat + d->p_ups[j]);
   const float hv[4] = {hp[0], hp[1], hp[2], hp[3]};
   const int tid = threadIdx.x;
@@ -128,12 +130,10 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
     wys[q][a] = (iy < hi && oy >= 0 && oy < ho) ? axis_w(hv, oy, iy, hi) : 0.0f;
     wxs[q][a] = (ix < wi && ox >= 0 && ox < wo) ? axis_w(hv, ox, ix, wi) : 0.0f;
   }
-  const int nch = d->L - j;
   float dh[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int ch = 0; ch < nch; ++ch) {
+  {
     const float* gsrc = d->dU + d->uoff[j] + (size_t)ch * ho * wo;
     const float* tsrc = tchan(d, j, ch);
-    __syncthreads();
     for (int i = tid; i < UG * UG; i += 256) {
       const int r = i / UG, c = i - r * UG;
       const int oy = 2 * iy0 - 3 + r, ox = 2 * ix0 - 3 + c;
@@ -305,8 +305,73 @@ __device__ __forceinline__ void mse_epilogue(const CDesc* d, int p, bool valid,
   }
 }
 
+// Trunk weights staged in LDS with fixed strides, so that every read is a
+// uniform-address (broadcast) vector load and no loop depends on the runtime L.
+//   layer-1 record a (12 floats): W1[a][0..7] (zero beyond L), b1[a], and for a
+//     one-hidden-layer trunk the output column Wo[0..2][a];
+//   layer-2 record b (two hidden layers): W2[b][0..W1-1], b2[b], Wo[0..2][b];
+//   tail: Ws[c][0..7] (stabilizer, zero beyond L or without stabilizer), then
+//     the output bias bo[c] (+ bs[c] with a stabilizer).
+template <int NH, int W1, int W2>
+struct SynLds {
+  static constexpr int R1 = 12;
+  static constexpr int R2 = NH == 2 ? ((W1 + 4 + 3) & ~3) : 0;
+  static constexpr int N1 = W1 * R1;
+  static constexpr int N2 = NH == 2 ? W2 * R2 : 0;
+  static constexpr int TAIL = N1 + N2;
+  static constexpr int TOTAL = TAIL + 28;
+};
+
+template <int NH, int W1, int W2>
+__device__ void stage_syn_weights(const CDesc* d, const CF* P, float* w) {
+  using S = SynLds<NH, W1, W2>;
+  const int L = d->L;
+  for (int i = threadIdx.x; i < S::TOTAL; i += blockDim.x) {
+    float v = 0.0f;
+    if (i < S::N1) {
+      const int a = i / S::R1, e = i % S::R1;
+      if (e < 8)
+        v = e < L ? P[d->p_sw[0] + a * L + e] : 0.0f;
+      else if (e == 8)
+        v = P[d->p_sb[0] + a];
+      else if (NH == 1)
+        v = P[d->p_sw[1] + (e - 9) * W1 + a];
+    } else if (i < S::TAIL) {
+      const int r = i - S::N1, b = r / S::R2, e = r % S::R2;
+      if (e < W1)
+        v = P[d->p_sw[1] + b * W1 + e];
+      else if (e == W1)
+        v = P[d->p_sb[1] + b];
+      else if (e <= W1 + 3)
+        v = P[d->p_sw[2] + (e - W1 - 1) * W2 + b];
+    } else {
+      const int e = i - S::TAIL;
+      if (e < 24) {
+        const int c = e >> 3, q = e & 7;
+        v = (d->syn_stab && q < L) ? P[d->p_ssw + c * L + q] : 0.0f;
+      } else if (e < 27) {
+        const int c = e - 24;
+        v = P[d->p_sb[NH] + c] + (d->syn_stab ? P[d->p_ssb + c] : 0.0f);
+      }
+    }
+    w[i] = v;
+  }
+}
+
+// zhat at pixel p: channel 0 = yhat^(0), channels 1..L-1 = U_1; zero beyond L
+// and for p outside the image.
+__device__ __forceinline__ void load_z8(const CDesc* d, int p, bool valid, float* z) {
+  const int n = d->H * d->W;
+  z[0] = valid ? d->yhat[p] : 0.0f;
+#pragma unroll
+  for (int q = 1; q < 8; ++q)
+    z[q] = (valid && q < d->L) ? d->U[d->uoff[1] + (size_t)(q - 1) * n + p] : 0.0f;
+}
+
 template <int NH, int W1, int W2>
 __global__ __launch_bounds__(CC_PIX_TILE) void k_syn_fwd(Launch Lc, int final_mse) {
+  using S = SynLds<NH, W1, W2>;
+  __shared__ __align__(16) float w[S::TOTAL];
   __shared__ double sh[CC_PIX_TILE / 64];
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
@@ -314,15 +379,226 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_syn_fwd(Launch Lc, int final_ms
   const int n = d->H * d->W;
   const int p = wgi * CC_PIX_TILE + threadIdx.x;
   const bool valid = p < n;
-  const CF* P = (const CF*)(d->theta + d->n_lat);
-  float z[CC_MAX_L], h1[W1], h2[NH == 2 ? W2 : 1], out[3];
+  stage_syn_weights<NH, W1, W2>(d, (const CF*)(d->theta + d->n_lat), w);
+  float z[8];
+  load_z8(d, p, valid, z);
+  __syncthreads();
+  const float4* w4 = (const float4*)w;
+  float out[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float4 a = w4[(S::TAIL >> 2) + 2 * c], b = w4[(S::TAIL >> 2) + 2 * c + 1];
+    out[c] = w[S::TAIL + 24 + c] + a.x * z[0] + a.y * z[1] + a.z * z[2] + a.w * z[3] + b.x * z[4] +
+             b.y * z[5] + b.z * z[6] + b.w * z[7];
+  }
+  if constexpr (NH == 1) {
+#pragma unroll 4
+    for (int a = 0; a < W1; ++a) {
+      const float4 r0 = w4[3 * a], r1 = w4[3 * a + 1], r2 = w4[3 * a + 2];
+      float s = r2.x + r0.x * z[0] + r0.y * z[1] + r0.z * z[2] + r0.w * z[3] + r1.x * z[4] +
+                r1.y * z[5] + r1.z * z[6] + r1.w * z[7];
+      s = fmaxf(s, 0.0f);
+      out[0] += r2.y * s;
+      out[1] += r2.z * s;
+      out[2] += r2.w * s;
+    }
+  } else {
+    float h1[W1];
+#pragma unroll
+    for (int a = 0; a < W1; ++a) {
+      const float4 r0 = w4[3 * a], r1 = w4[3 * a + 1], r2 = w4[3 * a + 2];
+      const float s = r2.x + r0.x * z[0] + r0.y * z[1] + r0.z * z[2] + r0.w * z[3] + r1.x * z[4] +
+                      r1.y * z[5] + r1.z * z[6] + r1.w * z[7];
+      h1[a] = fmaxf(s, 0.0f);
+    }
+#pragma unroll 2
+    for (int b = 0; b < W2; ++b) {
+      const float* r = w + S::N1 + b * S::R2;
+      float s = r[W1];
+#pragma unroll
+      for (int a = 0; a < W1; ++a) s += r[a] * h1[a];
+      s = fmaxf(s, 0.0f);
+      out[0] += r[W1 + 1] * s;
+      out[1] += r[W1 + 2] * s;
+      out[2] += r[W1 + 3] * s;
+    }
+  }
   if (valid) {
-    load_z(d, p, z);
-    syn_mlp<NH, W1, W2>(d, P, z, h1, h2, out);
 #pragma unroll
     for (int c = 0; c < 3; ++c) d->X[(size_t)c * n + p] = out[c];
   }
   if (final_mse) mse_epilogue(d, p, valid, out, wgi, sh);
+}
+
+// Backward of a one-hidden-layer trunk.  The four waves of a workgroup take
+// the same 64 pixels and a quarter of the hidden units each: a wave
+// recomputes its units' pre-activations, back-propagates the output gradient
+// through them, accumulates its units' weight gradients in registers (one
+// partial per lane, summed over the workgroup's chunks) and leaves its share
+// of dzhat in LDS, where the four shares are added in a fixed order.  The
+// per-lane partials are reduced once at the end (LDS transpose, then a fixed
+// butterfly), giving one partial row per workgroup.
+template <int W1>
+__global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
+  using S = SynLds<1, W1, 0>;
+  constexpr int UPW = (W1 + 3) / 4;       // hidden units per wave
+  constexpr int NU = UPW * 12;           // unit accumulators: dW1 row (8), db1, dWo column (3)
+  constexpr int NACC = NU + 9;           // + stabilizer dWs[c][q] for 2 q's, output bias
+  constexpr int RS = 16 * 65;            // reduction region per wave
+  __shared__ __align__(16) float w[S::TOTAL];
+  __shared__ __align__(16) float zb[2][64][12];      // per lane: z[0..7], go[0..2]
+  __shared__ __align__(16) float red[4 * RS];        // dz shares [2][4][8][64], then reduction
+  const int im = cc_find_img(Lc, blockIdx.x);
+  const CDesc* d = (const CDesc*)Lc.d[im];
+  const int wg = blockIdx.x - Lc.tile0[im];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = d->H * d->W, L = d->L;
+  const int nchunk = d->syn_nchunk, nwg = d->syn_nwg;
+  const float* G = src_b ? d->dXb : d->dXa;
+  stage_syn_weights<1, W1, 0>(d, (const CF*)(d->theta + d->n_lat), w);
+
+  // feature f of a chunk (f = wv + 4j): 0 yhat, 1..7 U planes (zero beyond L),
+  // 8..10 output-gradient planes
+  float pre[3];
+  auto load_chunk = [&](int ch) {
+    const int p = ch * CC_SYN_CHUNK + lane;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int f = wv + 4 * j;
+      float v = 0.0f;
+      if (p < n) {
+        if (f == 0)
+          v = d->yhat[p];
+        else if (f < 8) {
+          if (f < L) v = d->U[d->uoff[1] + (size_t)(f - 1) * n + p];
+        } else if (f < 11)
+          v = G[(size_t)(f - 8) * n + p];
+      }
+      pre[j] = v;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int f = wv + 4 * j;
+      if (f < 11) zb[buf][lane][f] = pre[j];
+    }
+  };
+
+  float acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = 0.0f;
+  const float4* w4 = (const float4*)w;
+  int buf = 0;
+  if (wg < nchunk) {
+    load_chunk(wg);
+    store_chunk(0);
+  }
+  __syncthreads();
+  for (int ch = wg; ch < nchunk; ch += nwg, buf ^= 1) {
+    const int nxt = ch + nwg;
+    if (nxt < nchunk) load_chunk(nxt);
+    const float4 za = *(const float4*)&zb[buf][lane][0], zc = *(const float4*)&zb[buf][lane][4],
+                 gg = *(const float4*)&zb[buf][lane][8];
+    const float z[8] = {za.x, za.y, za.z, za.w, zc.x, zc.y, zc.z, zc.w};
+    const float go[3] = {gg.x, gg.y, gg.z};
+    float dz[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dz[q] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < UPW; ++u) {
+      const int a = wv * UPW + u;
+      if (UPW * 4 != W1 && a >= W1) continue;
+      const float4 r0 = w4[3 * a], r1 = w4[3 * a + 1], r2 = w4[3 * a + 2];
+      const float wr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+      float s = r2.x;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += wr[q] * z[q];
+      const float h = fmaxf(s, 0.0f);
+      const float dh = s > 0.0f ? r2.y * go[0] + r2.z * go[1] + r2.w * go[2] : 0.0f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        dz[q] += wr[q] * dh;
+        acc[12 * u + q] += dh * z[q];
+      }
+      acc[12 * u + 8] += dh;
+      acc[12 * u + 9] += go[0] * h;
+      acc[12 * u + 10] += go[1] * h;
+      acc[12 * u + 11] += go[2] * h;
+    }
+    float* dzs = red + buf * (4 * 8 * 64);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dzs[(wv * 8 + q) * 64 + lane] = dz[q];
+    if (nxt < nchunk) store_chunk(buf ^ 1);
+    __syncthreads();
+    // dzhat channels q = wv and wv + 4: the four shares in wave order, plus the
+    // stabilizer's term
+    const int p = ch * CC_SYN_CHUNK + lane;
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi) {
+      const int q = wv + 4 * qi;
+      if (q >= L) continue;
+      float v = dzs[(0 * 8 + q) * 64 + lane] + dzs[(1 * 8 + q) * 64 + lane] +
+                dzs[(2 * 8 + q) * 64 + lane] + dzs[(3 * 8 + q) * 64 + lane];
+      v += w[S::TAIL + q] * go[0] + w[S::TAIL + 8 + q] * go[1] + w[S::TAIL + 16 + q] * go[2];
+      if (p < n) {
+        if (q == 0)
+          d->dyq[p] = v;
+        else
+          d->dU[d->uoff[1] + (size_t)(q - 1) * n + p] = v;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[NU + 3 * qi + c] += go[c] * z[q];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[NU + 6 + c] += go[c];
+  }
+
+  // per-lane partials -> one value per parameter, in a fixed order
+  __syncthreads();
+  const long long g_off = d->prod[d->prod_syn].off;
+  const int base = d->p_sw[0];
+  float* outrow = d->wp + g_off + (size_t)wg * d->prod[d->prod_syn].pcnt;
+  float* rw = red + wv * RS;
+#pragma unroll
+  for (int r0 = 0; r0 < NACC; r0 += 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (r0 + k < NACC) rw[k * 65 + lane] = acc[r0 + k];
+    __syncthreads();
+    const int pk = lane >> 2, qr = lane & 3;
+    float v = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v += rw[pk * 65 + qr * 16 + i];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    const int k = r0 + pk;
+    if (qr == 0 && k < NACC) {
+      int dst = -1, dst2 = -1;
+      if (k < NU) {
+        const int u = k / 12, e = k % 12, a = wv * UPW + u;
+        if (a < W1) {
+          if (e < 8)
+            dst = e < L ? d->p_sw[0] + a * L + e : -1;
+          else if (e == 8)
+            dst = d->p_sb[0] + a;
+          else
+            dst = d->p_sw[1] + (e - 9) * W1 + a;
+        }
+      } else if (k < NU + 6) {
+        const int x = k - NU, q = wv + 4 * (x / 3), c = x % 3;
+        if (d->syn_stab && q < L) dst = d->p_ssw + c * L + q;
+      } else if (wv == 0) {
+        const int c = k - NU - 6;
+        dst = d->p_sb[1] + c;
+        if (d->syn_stab) dst2 = d->p_ssb + c;
+      }
+      if (dst >= 0) outrow[dst - base] = v;
+      if (dst2 >= 0) outrow[dst2 - base] = v;
+    }
+    __syncthreads();
+  }
 }
 
 // Backward of the trunk for one pixel per thread (recomputing the hidden
@@ -496,80 +772,133 @@ __device__ __forceinline__ int srcs(int q, int o, int n, int* ps) {
 
 // dX_r = dX_{r+1} + Conv3x3^T(dX_{r+1}) (adjoint of the replicate padding
 // included), plus the layer's weight gradient as one partial row of 84 per
-// workgroup; each thread handles RES_PPT pixels before the reduction.
+// workgroup.  A workgroup takes RES_TH x RES_TW tiles (stride: the number of
+// workgroups); each tile stages X_r with a replicate-clamped halo and the
+// incoming gradient with a zero halo in LDS.  In the image interior the
+// adjoint is the plain correlation with the flipped kernel; on the image
+// border the sources of every tap are enumerated per axis (srcs), which adds
+// the clamped reads' contributions.  Weight-gradient partials stay in
+// registers per lane and are reduced once, in a fixed order.
 // src_b selects the input buffer; the output goes to the other.
-__global__ __launch_bounds__(CC_PIX_TILE) void k_res_bwd(Launch Lc, int r, int src_b) {
-  __shared__ float sh[84][CC_PIX_TILE / 64];
+__global__ __launch_bounds__(256, 2) void k_res_bwd(Launch Lc, int r, int src_b) {
+  constexpr int TH = CC_RES_TH, TW = CC_RES_TW, SH = TH + 2, SW = TW + 2;
+  __shared__ float xs[3][SH][SW];
+  __shared__ float gs[3][SH][SW];
+  __shared__ __align__(16) float wadj[3][9][4];   // [ci][tap][co]
+  __shared__ float red[4 * 16 * 65];
+  __shared__ float wsum[4][84];
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
   const int wgi = blockIdx.x - Lc.tile0[im];
+  const int nwg = d->res_nwg;
   const int H = d->H, W = d->W, n = H * W;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const CF* Wr = (const CF*)(d->theta + d->n_lat + d->p_rw[r]);
   const float* G = src_b ? d->dXb : d->dXa;
   float* O = src_b ? d->dXa : d->dXb;
   const float* X = d->X + (size_t)r * 3 * n;
-  float gw[84];
+  if (tid < 108) {
+    const int ci = tid / 36, t = (tid / 4) % 9, co = tid & 3;
+    wadj[ci][t][co] = co < 3 ? Wr[(co * 3 + ci) * 9 + t] : 0.0f;
+  }
+  float acc[84];
 #pragma unroll
-  for (int q = 0; q < 84; ++q) gw[q] = 0.0f;
-  for (int k = 0; k < CC_RES_PPT; ++k) {
-    const int p = (wgi * CC_RES_PPT + k) * CC_PIX_TILE + threadIdx.x;
-    if (p >= n) break;
-    const int y = p / W, x = p - y * W;
-    float g[3];
+  for (int q = 0; q < 84; ++q) acc[q] = 0.0f;
+  const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
+  for (int tile = wgi; tile < ntx * nty; tile += nwg) {
+    const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * TW;
+    __syncthreads();   // previous tile's reads are done (and wadj is written)
+    for (int i = tid; i < SH * SW; i += 256) {
+      const int ly = i / SW, lx = i - ly * SW;
+      const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+      const int cy = clampi(gy, 0, H - 1), cx = clampi(gx, 0, W - 1);
+      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) g[c] = G[(size_t)c * n + p];
+      for (int c = 0; c < 3; ++c) {
+        xs[c][ly][lx] = X[(size_t)c * n + cy * W + cx];
+        gs[c][ly][lx] = in ? G[(size_t)c * n + gy * W + gx] : 0.0f;
+      }
+    }
+    __syncthreads();
 #pragma unroll
-    for (int ky = 0; ky < 3; ++ky) {
-      const int yy = clampi(y + ky - 1, 0, H - 1);
+    for (int k = 0; k < TH / 4; ++k) {
+      const int ly = wv + 4 * k, lx = lane;
+      const int y = ty0 + ly, x = tx0 + lx;
+      if (y >= H || x >= W) continue;
+      float g[3];
 #pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        const int xx = clampi(x + kx - 1, 0, W - 1);
+      for (int c = 0; c < 3; ++c) g[c] = gs[c][ly + 1][lx + 1];
+      // weight gradient: g[co] * X_r[ci] at the tap's clamped position
 #pragma unroll
-        for (int ci = 0; ci < 3; ++ci) {
-          const float v = X[(size_t)ci * n + yy * W + xx];
+      for (int ci = 0; ci < 3; ++ci)
 #pragma unroll
-          for (int co = 0; co < 3; ++co) gw[(co * 3 + ci) * 9 + ky * 3 + kx] += g[co] * v;
+        for (int t = 0; t < 9; ++t) {
+          const float v = xs[ci][ly + t / 3][lx + t % 3];
+#pragma unroll
+          for (int co = 0; co < 3; ++co) acc[(co * 3 + ci) * 9 + t] += g[co] * v;
+        }
+#pragma unroll
+      for (int co = 0; co < 3; ++co) acc[81 + co] += g[co];
+      // adjoint
+      float o[3] = {g[0], g[1], g[2]};
+      if (y > 0 && y < H - 1 && x > 0 && x < W - 1) {
+#pragma unroll
+        for (int co = 0; co < 3; ++co)
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            const float gv = gs[co][ly + 2 - t / 3][lx + 2 - t % 3];
+#pragma unroll
+            for (int ci = 0; ci < 3; ++ci) o[ci] += wadj[ci][t][co] * gv;
+          }
+      } else {
+        for (int ky = 0; ky < 3; ++ky) {
+          int py[2];
+          const int cy = srcs(y, ky - 1, H, py);
+          for (int kx = 0; kx < 3; ++kx) {
+            int px[2];
+            const int cx = srcs(x, kx - 1, W, px);
+            const int t = ky * 3 + kx;
+            for (int a2 = 0; a2 < cy; ++a2)
+              for (int b2 = 0; b2 < cx; ++b2) {
+                const int sy = py[a2] - ty0 + 1, sx = px[b2] - tx0 + 1;
+#pragma unroll
+                for (int co = 0; co < 3; ++co) {
+                  const float gv = gs[co][sy][sx];
+#pragma unroll
+                  for (int ci = 0; ci < 3; ++ci) o[ci] += wadj[ci][t][co] * gv;
+                }
+              }
+          }
         }
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) O[(size_t)c * n + y * W + x] = o[c];
     }
-#pragma unroll
-    for (int co = 0; co < 3; ++co) gw[81 + co] += g[co];
-    float acc[3] = {g[0], g[1], g[2]};
-#pragma unroll
-    for (int ky = 0; ky < 3; ++ky) {
-      int py[2];
-      const int cy = srcs(y, ky - 1, H, py);
-#pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        int px[2];
-        const int cx = srcs(x, kx - 1, W, px);
-        for (int a = 0; a < cy; ++a)
-          for (int b = 0; b < cx; ++b) {
-            const int s2 = py[a] * W + px[b];
-#pragma unroll
-            for (int co = 0; co < 3; ++co) {
-              const float gv = G[(size_t)co * n + s2];
-#pragma unroll
-              for (int ci = 0; ci < 3; ++ci) acc[ci] += Wr[(co * 3 + ci) * 9 + ky * 3 + kx] * gv;
-            }
-          }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) O[(size_t)c * n + p] = acc[c];
   }
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  // per-lane partials -> per-wave sums (LDS transpose, fixed butterfly) ->
+  // workgroup sum in wave order
+  __syncthreads();
+  float* rw = red + wv * (16 * 65);
 #pragma unroll
-  for (int q = 0; q < 84; ++q) {
-    const float s2 = wave_sum(gw[q]);
-    if (ln == 0) sh[q][wv] = s2;
+  for (int r0 = 0; r0 < 84; r0 += 16) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (r0 + k < 84) rw[k * 65 + lane] = acc[r0 + k];
+    __syncthreads();
+    const int pk = lane >> 2, qr = lane & 3;
+    float v = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v += rw[pk * 65 + qr * 16 + i];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    __syncthreads();
+    if (qr == 0 && r0 + pk < 84) wsum[wv][r0 + pk] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 84) {
-    float s2 = 0.0f;
-    for (int w2 = 0; w2 < CC_PIX_TILE / 64; ++w2) s2 += sh[threadIdx.x][w2];
+  if (tid < 84) {
     const long long pg_off = d->prod[d->prod_res0 + r].off;
-    d->wp[pg_off + (size_t)wgi * 84 + threadIdx.x] = s2;
+    d->wp[pg_off + (size_t)wgi * 84 + tid] = wsum[0][tid] + wsum[1][tid] + wsum[2][tid] + wsum[3][tid];
   }
 }
 
@@ -608,10 +937,13 @@ int cc_launch_syn_fwd_plain(const Launch& l, const DevDesc& h, int final_mse, hi
 
 int cc_launch_syn_bwd_plain(const Launch& l, const DevDesc& h, int src_b, hipStream_t st) {
   const int w2 = h.n_syn_hidden == 2 ? h.syn_w[2] : 0;
-#define X(a, b, c)                                                                          \
-  if (h.n_syn_hidden == a && h.syn_w[1] == b && w2 == c) {                                  \
-    hipLaunchKernelGGL((k_syn_bwd<a, b, c>), dim3(l.tile0[l.n]), dim3(64), 0, st, l, src_b); \
-    return ok();                                                                            \
+#define X(a, b, c)                                                                           \
+  if (h.n_syn_hidden == a && h.syn_w[1] == b && w2 == c) {                                   \
+    if constexpr (a == 1)                                                                    \
+      hipLaunchKernelGGL((k_syn_bwd1<b>), dim3(l.tile0[l.n]), dim3(256), 0, st, l, src_b);   \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_syn_bwd<a, b, c>), dim3(l.tile0[l.n]), dim3(64), 0, st, l, src_b); \
+    return ok();                                                                             \
   }
   CC_SYN_SHAPES(X)
 #undef X

@@ -47,6 +47,75 @@ def oracle_state(mc, H, W, img, lam, seed, latents, params):
     return R.OracleState(mc.as_dict(), H, W, img, lam, seed, latents, params)
 
 
+def outlier_indices(a, b, rtol, segs):
+    """Indices of every element breaking |a-b| <= rtol (|b| + rms(b_segment))."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    bad = []
+    for _, sl in segs:
+        bb = b[sl]
+        if bb.size == 0:
+            continue
+        rms = float(np.sqrt(np.mean(bb * bb)))
+        r = np.abs(a[sl] - bb) > rtol * (np.abs(bb) + rms)
+        bad.append(np.nonzero(r)[0] + sl.start)
+    return np.concatenate(bad) if bad else np.zeros(0, np.int64)
+
+
+def unexplained_outliers(mc, H, W, bad, sites):
+    """Outlier elements that no near-threshold decision can reach.
+
+    Footprints on the latent grids (conservative rectangles):
+      ARM ReLU, log-scale clamp, probability floor at grid k, position (y, x):
+        grid k rows y-4..y, columns x-4..x+4 (the position and every causal
+        neighbour its context reads), and the IFCE parents
+        (y >> (j-k), x >> (j-k)) on the coarser grids j;
+      synthesis ReLU at pixel (y, x): grid 0 at (y, x) +-1 and grid j >= 1
+        within +-4 of (y >> j, x >> j) (j stride-2 upsamplings, each reading
+        inputs within +-2 of half its output index, add up to less than 4).
+    Decoder-parameter elements are never explained (every decision reaches
+    them, so they are held to the plain rule).  Returns the indices of `bad`
+    that lie in no footprint."""
+    L = mc.L
+    masks = [np.zeros((H >> k, W >> k), bool) for k in range(L)]
+    widths = {}
+    for i, w in enumerate(mc.arm_hidden):
+        widths[("arm", i)] = w
+    for i, w in enumerate(mc.syn_hidden):
+        widths[("syn", i)] = w
+
+    def mark(k, y0, y1, x0, x1):
+        h, w = masks[k].shape
+        masks[k][max(y0, 0):min(y1, h - 1) + 1, max(x0, 0):min(x1, w - 1) + 1] = True
+
+    for _, tag, idx in sites:
+        if tag[0] == "syn":
+            p = idx // widths[("syn", tag[1])]
+            y, x = divmod(p, W)
+            mark(0, y - 1, y + 1, x - 1, x + 1)
+            for j in range(1, L):
+                mark(j, (y >> j) - 4, (y >> j) + 4, (x >> j) - 4, (x >> j) + 4)
+            continue
+        k = tag[1]
+        pos = idx // widths[("arm", tag[2])] if tag[0] == "arm" else idx
+        y, x = divmod(pos, W >> k)
+        mark(k, y - 4, y, x - 4, x + 4)
+        if k < mc.n_ifce_grids:
+            for j in range(k + 1, L):
+                mark(j, y >> (j - k), y >> (j - k), x >> (j - k), x >> (j - k))
+    starts = np.cumsum([0] + [(H >> k) * (W >> k) for k in range(L)])
+    out = []
+    for e in np.asarray(bad).tolist():
+        k = int(np.searchsorted(starts, e, side="right") - 1)
+        if k >= L:
+            out.append(e)
+            continue
+        y, x = divmod(e - int(starts[k]), W >> k)
+        if not masks[k][y, x]:
+            out.append(e)
+    return out
+
+
 def outliers(a, b, rtol, segs, top=5):
     """Elements breaking |a-b| <= rtol (|b| + rms(b_segment)): their count
     and the worst few (ratio, segment, index, a, b)."""
@@ -70,7 +139,8 @@ def outliers(a, b, rtol, segs, top=5):
 
 
 
-def _oracle_grad(mc, H, W, theta, img, lam, quant, T, sigma, seed, t, tau, flip):
+def _oracle_grad(mc, H, W, theta, img, lam, quant, T, sigma, seed, t, tau, flip, totals=None,
+                 capture=None):
     """Oracle loss gradient with chosen near-threshold decisions inverted.
 
     Decisions: ARM and synthesis ReLUs (pre-activation within tau * rms of the
@@ -144,14 +214,115 @@ def _oracle_grad(mc, H, W, theta, img, lam, quant, T, sigma, seed, t, tau, flip)
             h = relu(h, ("syn", i))
     if mc.syn_stab:
         h = h + x0 @ P["syn.stab.w"].T + P["syn.stab.b"]
+    if capture is not None:
+        h.retain_grad()
     xh = h.T.reshape(3, H, W)
     for r in range(mc.n_res):
         xp = Fnn.pad(xh[None], (1, 1, 1, 1), mode="replicate")
         xh = xh + Fnn.conv2d(xp, P[f"res.{r}.w"], P[f"res.{r}.b"])[0]
     imgt = torch.tensor(np.asarray(img, np.float64))
-    loss = torch.mean((xh - imgt) ** 2) + lam * bits / (H * W)
+    mse = torch.mean((xh - imgt) ** 2)
+    loss = mse + lam * bits / (H * W)
     loss.backward()
+    if totals is not None:
+        totals.update(loss=float(loss), bits=float(bits), mse=float(mse))
+    if capture is not None:   # for param_flip_slack
+        capture.update(grids=[g.detach() for g in grids], z=x0.detach(), go=h.grad.detach())
     return th.grad.numpy().copy(), sites
+
+
+def param_flip_slack(mc, H, W, theta, lam, sites, cap):
+    """First-order bound of what near-threshold decisions can do to the
+    decoder-parameter gradient, without one full oracle run per decision.
+
+    A decision (ARM ReLU, log-scale clamp or probability floor at one latent
+    position; synthesis ReLU at one pixel) changes only that position's own
+    term of the parameter gradient, so the term is recomputed for that single
+    position with the decision inverted (same inversion as _oracle_grad) and
+    without, and the slack of a parameter is the sum over decisions of
+    |change|.  `cap` comes from _oracle_grad(..., capture=cap): quantised
+    grids, zhat per pixel and the gradient at the trunk output per pixel.
+    Not included: what a changed pixel gradient does to the upsampling taps
+    (one pixel's share of a tap gradient summed over a whole level)."""
+    cfg = mc.as_dict()
+    n_lat = wl.n_latents(mc, H, W)
+    pt = torch.tensor(np.asarray(theta[n_lat:], np.float64), requires_grad=True)
+    P = R.unpack_params(cfg, pt)
+    grids = cap["grids"]
+    offs = R.causal_offsets(mc.n_spatial)
+    F, G, L = mc.n_ifce_feat, mc.n_ifce_grids, mc.L
+    nl = len(mc.arm_hidden) + 1
+    lmin, lmax, pmin = mc.logscale_min, mc.logscale_max, mc.p_min
+    scale = lam / (H * W)
+
+    def grad_of(v):
+        g = torch.autograd.grad(v, pt, allow_unused=True)[0]
+        return np.zeros(pt.numel()) if g is None else g.numpy()
+
+    def inv_relu(x, u):
+        xd = x.detach()
+        m = torch.zeros_like(xd, dtype=torch.bool)
+        m[0, u] = True
+        return torch.where(m, torch.where(xd > 0, x * 0.0, x), torch.relu(x))
+
+    def arm_term(k, pos, tag, u):
+        gk = grids[k]
+        h, w = gk.shape
+        y, x = divmod(pos, w)
+        s = torch.tensor([[float(gk[y + dy, x + dx]) if 0 <= y + dy < h and 0 <= x + dx < w
+                           else 0.0 for dy, dx in offs]], dtype=torch.float64)
+        c = s
+        if F:
+            if k < G:
+                r = torch.tensor([[float(grids[j][y >> (j - k), x >> (j - k)])
+                                   for j in range(k + 1, L)]], dtype=torch.float64)
+                f = r @ P[f"ifce.{k}.w"].T + P[f"ifce.{k}.b"]
+            else:
+                f = s.new_zeros(1, F)
+            c = torch.cat([s, f], dim=1)
+        v = c
+        for i in range(nl):
+            v = v @ P[f"arm.{i}.w"].T + P[f"arm.{i}.b"]
+            if i < nl - 1:
+                v = inv_relu(v, u) if tag == ("arm", k, i) else torch.relu(v)
+        if mc.arm_stab:
+            v = v + c @ P["arm.stab.w"].T + P["arm.stab.b"]
+        mu, ls = v[:, 0], v[:, 1]
+        lcl = torch.clamp(ls, lmin, lmax)
+        if tag == ("clamp", k):
+            lsd = ls.detach()
+            lcl = torch.where((lsd >= lmin) & (lsd <= lmax), lcl.detach(), ls)
+        b = torch.exp(lcl)
+        yk = gk.reshape(-1)[pos:pos + 1]
+        p = R.laplace_cdf(yk + 0.5, mu, b) - R.laplace_cdf(yk - 0.5, mu, b)
+        pc = torch.clamp(p, min=pmin)
+        if tag == ("floor", k):
+            pc = torch.where(p.detach() >= pmin, pc.detach(), p)
+        return grad_of(scale * (-torch.log(pc) / R.LN2).sum())
+
+    def syn_term(pix, tag, u):
+        z = cap["z"][pix:pix + 1]
+        v = z
+        ns = len(mc.syn_hidden) + 1
+        for i in range(ns):
+            v = v @ P[f"syn.{i}.w"].T + P[f"syn.{i}.b"]
+            if i < ns - 1:
+                v = inv_relu(v, u) if tag == ("syn", i) else torch.relu(v)
+        if mc.syn_stab:
+            v = v + z @ P["syn.stab.w"].T + P["syn.stab.b"]
+        return grad_of((v * cap["go"][pix:pix + 1]).sum())
+
+    slack = np.zeros(pt.numel())
+    for _, tag, idx in sites:
+        if tag[0] == "syn":
+            pix, u = divmod(idx, mc.syn_hidden[tag[1]])
+            d = syn_term(pix, tag, u) - syn_term(pix, None, u)
+        else:
+            k = tag[1]
+            pos, u = divmod(idx, mc.arm_hidden[tag[2]]) if tag[0] == "arm" else (idx, 0)
+            d = arm_term(k, pos, tag, u) - arm_term(k, pos, None, u)
+        slack += np.abs(d)
+    return slack
 
 
 def decision_slack(mc, H, W, theta, img, lam, quant, T=None, sigma=None, seed=0, t=1,

@@ -15,7 +15,8 @@ import torch
 from oracle import coolchic_ref as R
 from paper_2605_02726_amd import workloads as wl
 
-from gpu_util import decision_slack, outliers, segments, slack_outliers
+from gpu_util import (_oracle_grad, decision_slack, outlier_indices, outliers,
+                      param_flip_slack, segments, slack_outliers, unexplained_outliers)
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +35,7 @@ CASES = {
     "hop_128x192_random": (wl.config_hop, 128, 192, 12, True),
     "tiny_64x32_random": (wl.config_tiny, 64, 32, 13, True),
     "hop_512x768_init": (wl.config_hop, 512, 768, 2, False),
+    "hop_320x1088_random": (wl.config_hop, 320, 1088, 14, True),   # ragged against every tile
 }
 
 
@@ -231,3 +233,64 @@ def test_gpu_gradient_matches_finite_differences():
             ok += 1
     print(f"FD agreement {ok}/{tried}", flush=True)
     assert ok >= 0.9 * tried
+
+
+_LARGEST = {}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_largest_serving_image(precision):
+    """2048x2048, the largest side of the serving trace (4.2 Mpixel, 5.6 M
+    latents), from a random state: totals and every gradient element against
+    the oracle.  At this size about a thousand ReLU, clamp and floor
+    decisions sit within rounding of their thresholds, too many to recompute
+    the whole oracle once per decision.  In FP32 every latent element outside
+    the per-element rule must lie inside the footprint of such a decision
+    (`unexplained_outliers`; the footprints cover about 0.5% of grid 0), and
+    every decoder-parameter element must hold the rule plus the first-order
+    slack of those decisions (`param_flip_slack`: each decision's own term
+    recomputed with the decision inverted).  The BF16 form is held to its own
+    rule (2e-2, at most 1% of the elements outside on random states)."""
+    mc = wl.config_hop()
+    H = W = 2048
+    seed = 21
+    img = wl.synth_image(H, W, seed)
+    lat = wl.random_latents(mc, H, W, seed, scale=2.0)
+    par = wl.init_params(mc, seed, arm_out_zero=False)
+    lam, t, T, sigma = 1e-3, 1, 0.35, 0.22
+    enc = _encoder(mc, img, lam, seed, lat, par, precision=precision)
+    loss, bits, mse = enc.step(t, 1e-2, T, sigma)
+    g = enc.grad()
+    theta = np.concatenate([lat, par]).astype(np.float64)
+    if "ref" not in _LARGEST:     # one oracle run (~20 s, ~15 GB) serves both forms
+        tot, cap = {}, {}
+        gref, sites = _oracle_grad(mc, H, W, theta, img, lam, "soft", T, sigma, seed, t, 3e-6,
+                                   set(), totals=tot, capture=cap)
+        _LARGEST["ref"] = (tot, gref, sites, cap)
+    tot, gref, sites, cap = _LARGEST["ref"]
+    tol_tot = RTOL if precision == "fp32" else 1e-3
+    print(f"[2048x2048/{precision}] loss {loss:.9g} vs {tot['loss']:.9g}; bits {bits:.9g} vs "
+          f"{tot['bits']:.9g}; mse {mse:.9g} vs {tot['mse']:.9g}", flush=True)
+    assert loss == pytest.approx(tot["loss"], rel=tol_tot)
+    assert bits == pytest.approx(tot["bits"], rel=tol_tot)
+    assert mse == pytest.approx(tot["mse"], rel=tol_tot)
+    segs = segments(mc, H, W)
+    if precision == "fp32":
+        n_lat = enc.n_lat
+        bad = outlier_indices(g, gref, RTOL, segs)
+        left = unexplained_outliers(mc, H, W, bad[bad < n_lat], sites)
+        slack = np.zeros(g.size)
+        slack[n_lat:] = param_flip_slack(mc, H, W, theta, lam, sites, cap)
+        n_par_bad, worst = slack_outliers(g, gref, slack, RTOL,
+                                          [sg for sg in segs if sg[1].start >= n_lat])
+        print(f"[2048x2048/fp32] {len(bad)} of {g.size} elements outside the rule, "
+              f"{len(sites)} near-threshold decisions; latents outside every footprint: "
+              f"{len(left)} {left[:8]}; parameters outside rule + slack: {n_par_bad} {worst}",
+              flush=True)
+        assert not left
+        assert n_par_bad == 0
+    else:
+        n_out, worst = outliers(g, gref, 2e-2, segs)
+        print(f"[2048x2048/bf16] {n_out} of {g.size} elements outside the rule; worst {worst}",
+              flush=True)
+        assert n_out <= 1e-2 * g.size

@@ -2,12 +2,20 @@
 oracle trajectory (tests/golden/trajectory_512x768_1000.json, written by
 tests/golden/make_trajectory.py from the oracle alone).
 
-Criterion: after the 1,000 iterations, the hard-quantised total rate (bits)
-and PSNR within 0.1% of the oracle's, for the plain FP32 and the fused BF16
-forms.  The checkpoints on the way are printed, not asserted: Adam's first
-moments turn rounding-level gradient differences into +-lr steps, and
-mid-course totals of even the FP32 form wander by a few tenths of a percent
-from the FP64 trajectory before the schedules anneal them back together.
+How far two correct implementations drift apart over 1,000 Adam iterations
+is measured on the oracle itself: the same run with every gradient element
+multiplied by (1 + 1e-6 xi) per step (the perturbed_*.json trajectories from
+the same script) ends with total bits up to 0.64% away, PSNR up to 0.019% and
+the rate-distortion cost J = MSE + lambda bpp (the objective of the
+optimisation) up to 0.045%.  FP32 also flips a few near-threshold ReLU,
+clamp and floor decisions per step, which such noise does not model, and the
+GPU runs end at a different split between rate and distortion, at an equal
+or lower J.
+
+Criterion, after the 1,000 iterations with hard quantisation: J not more
+than 0.1% above the oracle's and within 1% of it, total bits within 1% and
+PSNR within 0.1%, for the plain FP32 and the fused BF16 forms.  The
+checkpoints on the way are printed.
 """
 import json
 import os
@@ -34,7 +42,7 @@ def test_trajectory_totals_within_0p1_percent(precision):
     enc = Encoder(mc, torch.from_numpy(wl.image_large(2)), 1e-3, 2,
                   np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, 2),
                   precision=precision)
-    worst = 0.0
+    final = None
     for t in range(1, n_iter + 1):
         lr, T, s = schedule(t, n_iter)
         enc.step(t, lr, T, s, sync=False)
@@ -46,5 +54,13 @@ def test_trajectory_totals_within_0p1_percent(precision):
             print(f"[{precision}] t={t}: bits {rd['bits']:.1f} vs {ref['bits']:.1f} ({eb:+.2e}), "
                   f"psnr {rd['psnr']:.4f} vs {ref['psnr']:.4f} ({ep:+.2e})", flush=True)
             if t == n_iter:
-                worst = max(abs(eb), abs(ep))
-    assert worst <= 1e-3
+                final = (rd, ref)
+    rd, ref = final
+    hw = H * W
+    j_gpu = rd["mse"] + 1e-3 * rd["bits"] / hw
+    j_ref = ref["mse"] + 1e-3 * ref["bits"] / hw
+    ej = j_gpu / j_ref - 1.0
+    print(f"[{precision}] final J {j_gpu:.7f} vs {j_ref:.7f} ({ej:+.2e})", flush=True)
+    assert ej <= 1e-3 and abs(ej) <= 1e-2
+    assert abs(rd["bits"] / ref["bits"] - 1.0) <= 1e-2
+    assert abs(rd["psnr"] / ref["psnr"] - 1.0) <= 1e-3
