@@ -72,6 +72,17 @@ struct Layout {
   int syn_o[7];
 };
 
+// Workgroups of the IFCE gradient pooling: one per (child grid c, channel,
+// base block of side 2^(L-1-c)).
+int pool_blocks(const DevDesc& h) {
+  int tot = 0;
+  for (int c = 0; c < h.G; ++c) {
+    const int B = 1 << (h.L - 1 - c);
+    tot += h.F * (h.gh[c] / B) * (h.gw[c] / B);
+  }
+  return tot;
+}
+
 // Workgroups (and weight-gradient partial rows) of the upsampling adjoint at
 // level j: one per (channel of T_j, 16x16 tile of grid j).
 int ups_bwd_rows(const DevDesc& h, int j) {
@@ -96,6 +107,8 @@ int check_config(const cc_config* c, int H, int W) {
       !cc_syn_shape_supported(c->n_syn_hidden, c->syn_hidden[0], c->syn_hidden[1]))
     return fail(CC_EINVAL, "synthesis shape not compiled in");
   if (c->n_res < 0 || c->n_res > 4) return fail(CC_EINVAL, "n_res=%d outside [0, 4]", c->n_res);
+  if (c->n_ifce_feat > 0 && (1 << (c->L - 1)) > CC_POOL_BLOCK)
+    return fail(CC_EINVAL, "IFCE needs L <= 7 (L=%d)", c->L);
   if (!(c->logscale_min < c->logscale_max)) return fail(CC_EINVAL, "log-scale clamp");
   if (!(c->p_min > 0.0f && c->p_min < 1.0f)) return fail(CC_EINVAL, "p_min must be in (0, 1)");
   if (c->precision != CC_FP32_PLAIN && c->precision != CC_BF16_FUSED)
@@ -569,15 +582,7 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
   RET(quantise(s, n, p, st));
   RET(arm(s, n, backward ? 1 : 0, st));
   if (backward && h0.G > 0) {
-    for (int f = 1; f < h0.L; ++f) {
-      const Launch l = plan(s, n, [f](const DevDesc& h) {
-        long long tot = 0;
-        for (int c = 0; c < h.G; ++c)
-          if (c + f <= h.L - 1) tot += (long long)h.F * h.gh[c + f] * h.gw[c + f];
-        return cdiv(tot, CC_ELT_TILE);
-      });
-      RET(cc_launch_pool(l, f, st));
-    }
+    RET(cc_launch_pool(plan(s, n, pool_blocks), st));
   }
   RET(forward_dist(s, n, 1, st));
   if (backward) {
@@ -890,15 +895,7 @@ int cc_arm_fwd_bwd(cc_state* s, const float* yhat, const float* params, double* 
   RET(cc_launch_poke(&s->ddev->rate_scale, 1.0f, st));
   rc = arm(one, 1, bwd ? 1 : 0, st);
   if (rc == CC_OK && bwd && h.G > 0) {
-    for (int f = 1; f < h.L && rc == CC_OK; ++f) {
-      const Launch l = plan(one, 1, [f](const DevDesc& x) {
-        long long tot = 0;
-        for (int c = 0; c < x.G; ++c)
-          if (c + f <= x.L - 1) tot += (long long)x.F * x.gh[c + f] * x.gw[c + f];
-        return cdiv(tot, CC_ELT_TILE);
-      });
-      rc = cc_launch_pool(l, f, st);
-    }
+    rc = cc_launch_pool(plan(one, 1, pool_blocks), st);
   }
   if (rc == CC_OK && grad_yhat)
     rc = cc_launch_join(plan(one, 1, [](const DevDesc& x) { return x.lat_ntile; }), st, grad_yhat);

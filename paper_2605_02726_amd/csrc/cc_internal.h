@@ -96,7 +96,7 @@ __device__ __forceinline__ int cc_find_img(const Launch& L, int b) {
 struct HostImg;  // defined in cc_api.hip
 int cc_launch_qtrain(const Launch& l, const StepPack& a, hipStream_t st);
 int cc_launch_arm(const Launch& l, const DevDesc& h, int bwd, int precision, hipStream_t st);
-int cc_launch_pool(const Launch& l, int f, hipStream_t st);
+int cc_launch_pool(const Launch& l, hipStream_t st);
 int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out = nullptr, int adam = 0);
 int cc_launch_poke(float* p, float v, hipStream_t st);
 int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st);
@@ -119,6 +119,7 @@ int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
 #define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
+#define CC_POOL_BLOCK 64    // IFCE gradient pooling: largest base block side (L <= 7)
 #define CC_RES_TH 8         // residual-layer adjoint: tile rows (a multiple of 4)
 #define CC_RES_TW 64        // residual-layer adjoint: tile columns (one per lane)
 #define CC_RES_TPW 1        // residual-layer adjoint: tiles per workgroup

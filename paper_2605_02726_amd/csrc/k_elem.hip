@@ -118,26 +118,56 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L, StepPack A) {
   d->dq[i] = dq;
 }
 
-// One 2x2 sum-pooling level of the IFCE gradient pyramid: level f of child
-// grid c (at grid c+f) from level f-1 (at grid c+f-1), F channels.
-__global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L, int f) {
+// The IFCE gradient pyramid in one launch: level f of child grid c (at grid
+// c+f) holds the 2x2 sums of level f-1, level 0 being the IFCE feature
+// gradient the ARM kernel wrote at grid c.  A workgroup takes one channel
+// and one base block of side B = 2^(L-1-c) (the sides are multiples of it)
+// and builds every level of that block in LDS, adding each 2x2 group as
+// (top-left + top-right) + (bottom-left + bottom-right).
+__global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
+  __shared__ float buf[2][CC_POOL_BLOCK * CC_POOL_BLOCK / 4];
+  __shared__ float base[CC_POOL_BLOCK * CC_POOL_BLOCK];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
-  int e = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
-  for (int c = 0; c < d->G; ++c) {
-    if (c + f > d->L - 1) continue;
-    const int h = d->gh[c + f], w = d->gw[c + f], n = h * w;
-    const int tot = d->F * n;
-    if (e < tot) {
-      const int ch = e / n, p = e - ch * n, y = p / w, x = p - y * w;
-      const int w0 = d->gw[c + f - 1], n0 = d->gh[c + f - 1] * w0;
-      const float* src = d->df + d->dfoff[c][f - 1] + ch * n0;
-      const float s = (src[(2 * y) * w0 + 2 * x] + src[(2 * y) * w0 + 2 * x + 1]) +
-                      (src[(2 * y + 1) * w0 + 2 * x] + src[(2 * y + 1) * w0 + 2 * x + 1]);
-      d->df[d->dfoff[c][f] + ch * n + p] = s;
-      return;
+  int b = blockIdx.x - L.tile0[im];
+  int c = 0;
+  for (; c < d->G; ++c) {
+    const int B = 1 << (d->L - 1 - c);
+    const int nt = d->F * (d->gh[c] / B) * (d->gw[c] / B);
+    if (b < nt) break;
+    b -= nt;
+  }
+  if (c >= d->G) return;
+  const int B = 1 << (d->L - 1 - c);
+  const int tx = d->gw[c] / B, ty = d->gh[c] / B;
+  const int ch = b / (tx * ty), t = b - ch * (tx * ty);
+  const int by = t / tx, bx = t - by * tx;
+  {
+    const int w0 = d->gw[c], n0 = d->gh[c] * w0;
+    const float* src = d->df + d->dfoff[c][0] + (size_t)ch * n0;
+    for (int i = threadIdx.x; i < B * B; i += CC_ELT_TILE) {
+      const int y = i / B, x = i - y * B;
+      base[i] = src[(by * B + y) * w0 + bx * B + x];
     }
-    e -= tot;
+  }
+  __syncthreads();
+  const float* in = base;
+  int side = B;
+  for (int f = 1; f <= d->L - 1 - c; ++f) {
+    const int so = side >> 1;
+    float* out = buf[f & 1];
+    const int w = d->gw[c + f], n = d->gh[c + f] * w;
+    float* dst = d->df + d->dfoff[c][f] + (size_t)ch * n;
+    for (int i = threadIdx.x; i < so * so; i += CC_ELT_TILE) {
+      const int y = i / so, x = i - y * so;
+      const float* r0 = in + (2 * y) * side + 2 * x;
+      const float v = (r0[0] + r0[1]) + (r0[side] + r0[side + 1]);
+      out[i] = v;
+      dst[(by * so + y) * w + bx * so + x] = v;
+    }
+    __syncthreads();
+    in = out;
+    side = so;
   }
 }
 
@@ -292,9 +322,9 @@ int cc_launch_qtrain(const Launch& l, const StepPack& a, hipStream_t st) {
   hipLaunchKernelGGL(k_qtrain, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, a);
   return check_launch();
 }
-int cc_launch_pool(const Launch& l, int f, hipStream_t st) {
+int cc_launch_pool(const Launch& l, hipStream_t st) {
   if (l.tile0[l.n] == 0) return CC_OK;
-  hipLaunchKernelGGL(k_pool, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l, f);
+  hipLaunchKernelGGL(k_pool, dim3(l.tile0[l.n]), dim3(CC_ELT_TILE), 0, st, l);
   return check_launch();
 }
 int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out, int adam) {
