@@ -17,6 +17,11 @@ Parity status by function (see the tests under tests/test_oracle_*.py):
   forward, loss_and_grad         pinned (closed-form totals, central finite
                                  differences)
   adam                           pinned (first- and second-step closed forms)
+  soap (SoapState)               pinned (eigenbases at the first call,
+                                 constant-gradient closed form, reduction to
+                                 elementwise Adam for diagonal gradients,
+                                 equivariance under orthogonal changes of
+                                 basis, refresh as power iteration, einsum)
   multi-step trajectories        parity unpinned beyond the per-step pins
 """
 from .coolchic_ref import *  # noqa: F401,F403

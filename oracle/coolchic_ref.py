@@ -343,8 +343,15 @@ def adam(theta, g, m, v, t: int, lr: float, mask=None):
 class OracleState:
     """Encoder state: theta = [latents, params], Adam moments, last t."""
 
-    def __init__(self, cfg, H, W, img, lam, seed, latents, params):
+    def __init__(self, cfg, H, W, img, lam, seed, latents, params, optimizer="adam"):
         self.cfg, self.H, self.W = cfg, H, W
+        # decoder-parameter optimiser: Adam, or SOAP (Section IV-B; oracle/soap.py)
+        self.soap = None
+        if optimizer == "soap":
+            from .soap import SoapState
+            self.soap = SoapState(cfg)
+        elif optimizer != "adam":
+            raise ValueError(optimizer)
         self.img = np.asarray(img, dtype=np.float64)
         self.lam, self.seed = float(lam), int(seed)
         self.n_lat = sum(h * w for h, w in grid_shapes(cfg, H, W))
@@ -366,7 +373,14 @@ class OracleState:
         if not update_latents:
             mask = np.zeros(self.theta.shape, dtype=bool)
             mask[self.n_lat:] = True
-        self.theta, self.m, self.v = adam(self.theta, g, self.m, self.v, t, lr, mask)
+        if self.soap is not None:
+            # Adam on the latents, SOAP on the decoder parameters
+            lat = np.zeros(self.theta.shape, dtype=bool)
+            lat[:self.n_lat] = update_latents
+            self.theta, self.m, self.v = adam(self.theta, g, self.m, self.v, t, lr, lat)
+            self.theta[self.n_lat:] = self.soap.step(self.theta[self.n_lat:], g[self.n_lat:], lr)
+        else:
+            self.theta, self.m, self.v = adam(self.theta, g, self.m, self.v, t, lr, mask)
         self.t = t
         self.last_grad = g
         return loss, bits, mse
