@@ -57,7 +57,7 @@ def arm_flops_per_step(mc, H, W):
     return tot
 
 
-def measure_step(precision, steps, warmup, timing=True):
+def measure_step(precision, steps, warmup, timing=True, optimizer="adam"):
     import ctypes as C
     import numpy as np
     import torch
@@ -68,7 +68,8 @@ def measure_step(precision, steps, warmup, timing=True):
     H, W, seed, lam, n_iter = 512, 768, 2, 1e-3, 1000
     img = torch.from_numpy(wl.image_large(seed))
     lat = np.zeros(wl.n_latents(mc, H, W), np.float32)
-    enc = Encoder(mc, img, lam, seed, lat, wl.init_params(mc, seed), precision=precision)
+    enc = Encoder(mc, img, lam, seed, lat, wl.init_params(mc, seed), precision=precision,
+                  optimizer=optimizer)
     L = _lib.lib()
     t = 0
     for _ in range(warmup):
@@ -218,6 +219,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=16, help="serving trace length (0 = skip)")
     ap.add_argument("--serve-iters", type=int, default=2000)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-soap", action="store_true", help="skip the SOAP form of the step")
     ap.add_argument("--only-step", action="store_true",
                     help="time only the single-image step (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -227,6 +229,7 @@ def main():
         print(json.dumps(copy_calibration()))
         return
     if args.only_step:
+        args.no_soap = True
         args.batch_steps = 0
         args.serve_requests = 0
         args.cpu_steps = 0
@@ -244,6 +247,12 @@ def main():
         forms[p] = measure_step(p, args.steps, args.warmup, not args.no_kernel_timing)
     head = "bf16" if "bf16" in forms else "fp32"
     main_f = forms[head]
+    if not args.no_soap:
+        # the same step with SOAP on the decoder parameters (Section IV-B)
+        f = measure_step(head, args.steps, args.warmup, False, optimizer="soap")
+        f["optimizer"] = "soap (decoder parameters), adam (latents)"
+        f["overhead_vs_adam"] = round(f["ms_per_step"] / main_f["ms_per_step"] - 1.0, 4)
+        forms[head + "_soap"] = f
 
     mc = wl.config_hop()
     H, W = 512, 768

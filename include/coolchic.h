@@ -53,6 +53,7 @@ enum {
 
 enum { CC_SOFT = 0, CC_HARD = 1 };              /* quantisation mode   */
 enum { CC_FP32_PLAIN = 0, CC_BF16_FUSED = 1 };  /* arithmetic of the MLPs */
+enum { CC_OPT_ADAM = 0, CC_OPT_SOAP = 1 };      /* decoder-parameter optimiser */
 
 #define CC_MAX_BATCH 32
 
@@ -153,6 +154,35 @@ int cc_debug_read(cc_state* s, const char* buffer, float* host, int64_t count, v
 
 /* Switch the arithmetic of the MLP kernels (CC_FP32_PLAIN / CC_BF16_FUSED). */
 int cc_set_precision(cc_state* s, int precision);
+
+/* Optimiser of the decoder parameters (Section IV-B trains them with SOAP,
+ * the latents with Adam).  CC_OPT_ADAM (default): the latents' Adam.
+ * CC_OPT_SOAP: SOAP (Vyas et al., 2024) with its published defaults --
+ * beta1 = beta2 = 0.95, factor average 0.95, eps 1e-8, basis refresh every
+ * 10 updates, bias correction -- one Kronecker factor per dimension of each
+ * weight tensor (dimensions up to 48), Adam in SOAP's step form for
+ * one-dimensional tensors; the first step after selecting SOAP only
+ * initialises its factors and bases.  Selecting SOAP clears its state
+ * (enqueued on `stream`).  Every state of one cc_encode_step_batch call must
+ * use the same optimiser.  CC_EINVAL for an unknown value or a parameter
+ * tensor above 1024 values. */
+int cc_set_optimizer(cc_state* s, int optimizer, void* stream);
+
+/* Floats of all SOAP Kronecker factors of a configuration (equally, of all
+ * bases): the size of the `p` and `q` buffers below.  Host only; -1 if the
+ * configuration is not supported. */
+int64_t cc_soap_factor_size(const cc_config* cfg);
+
+/* SOAP state to / from host memory, in the layout of the decoder parameters:
+ * m, v: first and second moments, n_params floats each (v in the rotated
+ * coordinates); p, q: every factor and every basis, row-major, tensor by
+ * tensor in parameter order, dimension by dimension (cc_soap_factor_size
+ * floats each); calls: SOAP calls made (0: the next call initialises).
+ * Any pointer may be NULL to skip that part.  Synchronises `stream`. */
+int cc_get_soap_state(cc_state* s, float* m, float* v, float* p, float* q, int* calls,
+                      void* stream);
+int cc_set_soap_state(cc_state* s, const float* m, const float* v, const float* p,
+                      const float* q, int calls, void* stream);
 
 /* Per-module forward and backward on caller buffers (for autograd
  * wrappers).  The state supplies the decoder shape and serves as workspace:

@@ -11,10 +11,12 @@ and the latents with Adam, without stating SOAP's settings.  Readings:
     beta 0.95, eps 1e-8, basis refresh every 10 updates, bias correction, no
     weight decay; the learning rate follows the latents' schedule;
   * every parameter tensor of two or more dimensions gets one Kronecker
-    factor per dimension d, P_d <- b P_d + (1 - b) G_(d) G_(d)^T with G_(d)
-    the mode-d unfolding of the gradient (for a matrix: G G^T and G^T G);
-    one-dimensional tensors (biases, upsampling taps) get no factor and so
-    run Adam in SOAP's step form;
+    factor per dimension d of size at most 48 (SOAP's bound on
+    preconditioned dimensions, lowered to the sizes these decoders have),
+    P_d <- b P_d + (1 - b) G_(d) G_(d)^T with G_(d) the mode-d unfolding of
+    the gradient (for a matrix: G G^T and G^T G); one-dimensional tensors
+    (biases, upsampling taps) get no factor and so run Adam in SOAP's step
+    form;
   * the first call only sets the factors to (1 - b) G_(d) G_(d)^T and each
     basis Q_d to the eigenvectors of its factor, by descending eigenvalue;
     no parameter moves;
@@ -44,6 +46,7 @@ BETA2 = 0.95
 PRECOND_BETA = 0.95
 EPS = 1e-8
 REFRESH = 10
+MAX_PRECOND_DIM = 48
 
 
 def tensors(cfg: Dict) -> List[Tuple[str, Tuple[int, ...], int]]:
@@ -58,14 +61,16 @@ def tensors(cfg: Dict) -> List[Tuple[str, Tuple[int, ...], int]]:
 def rotate(x: np.ndarray, qs: List[np.ndarray]) -> np.ndarray:
     """x' = x x_0 Q_0^T x_1 Q_1^T ...: x'[..i_d..] = sum_j Q_d[j, i_d] x[..j..]."""
     for d, q in enumerate(qs):
-        x = np.moveaxis(np.tensordot(q, x, axes=([0], [d])), 0, d)
+        if q is not None:
+            x = np.moveaxis(np.tensordot(q, x, axes=([0], [d])), 0, d)
     return x
 
 
 def rotate_back(x: np.ndarray, qs: List[np.ndarray]) -> np.ndarray:
     """Inverse of rotate: x[..i_d..] = sum_j Q_d[i_d, j] x'[..j..]."""
     for d, q in enumerate(qs):
-        x = np.moveaxis(np.tensordot(q, x, axes=([1], [d])), 0, d)
+        if q is not None:
+            x = np.moveaxis(np.tensordot(q, x, axes=([1], [d])), 0, d)
     return x
 
 
@@ -110,7 +115,7 @@ class SoapState:
         self.q = {n: [None] * len(s) for n, s, _ in self.layout}
 
     def preconditioned(self, name: str) -> bool:
-        return self.p[name][0] is not None
+        return any(p is not None for p in self.p[name])
 
     def step(self, theta: np.ndarray, grad: np.ndarray, lr: float) -> np.ndarray:
         """One call with the gradient of the decoder parameters; returns the
@@ -123,8 +128,9 @@ class SoapState:
                     continue
                 g = grad[off:off + int(np.prod(shape))].reshape(shape)
                 for d in range(len(shape)):
-                    self.p[name][d] = (1.0 - PRECOND_BETA) * unfold_outer(g, d)
-                    self.q[name][d] = eig_desc(self.p[name][d])
+                    if shape[d] <= MAX_PRECOND_DIM:
+                        self.p[name][d] = (1.0 - PRECOND_BETA) * unfold_outer(g, d)
+                        self.q[name][d] = eig_desc(self.p[name][d])
             self.started = True
             return theta
         self.s += 1
@@ -145,20 +151,24 @@ class SoapState:
             theta[off:off + n] -= scale * upd.reshape(-1)
             if self.preconditioned(name):
                 for d in range(len(shape)):
-                    self.p[name][d] = PRECOND_BETA * self.p[name][d] + \
-                        (1.0 - PRECOND_BETA) * unfold_outer(g, d)
+                    if self.p[name][d] is not None:
+                        self.p[name][d] = PRECOND_BETA * self.p[name][d] + \
+                            (1.0 - PRECOND_BETA) * unfold_outer(g, d)
                 if self.s % REFRESH == 0:
                     for d in range(len(shape)):
-                        self.q[name][d], self.v[name] = refresh(self.p[name][d], self.q[name][d],
-                                                                self.v[name], d)
+                        if self.p[name][d] is not None:
+                            self.q[name][d], self.v[name] = refresh(self.p[name][d], self.q[name][d],
+                                                                    self.v[name], d)
         return theta
 
     # flat export / import, in the layout order, for comparisons with the GPU
     def export(self) -> Dict[str, np.ndarray]:
         m = np.concatenate([self.m[n].reshape(-1) for n, _, _ in self.layout])
         v = np.concatenate([self.v[n].reshape(-1) for n, _, _ in self.layout])
-        p = [self.p[n][d].reshape(-1) for n, s, _ in self.layout if len(s) >= 2 for d in range(len(s))]
-        q = [self.q[n][d].reshape(-1) for n, s, _ in self.layout if len(s) >= 2 for d in range(len(s))]
+        p = [self.p[n][d].reshape(-1) for n, s, _ in self.layout if len(s) >= 2
+             for d in range(len(s)) if self.p[n][d] is not None]
+        q = [self.q[n][d].reshape(-1) for n, s, _ in self.layout if len(s) >= 2
+             for d in range(len(s)) if self.q[n][d] is not None]
         return dict(m=m, v=v, p=np.concatenate(p) if p else np.zeros(0),
                     q=np.concatenate(q) if q else np.zeros(0), s=self.s, started=self.started)
 
@@ -171,6 +181,8 @@ class SoapState:
             pm += n
             if len(shape) >= 2:
                 for d, k in enumerate(shape):
+                    if k > MAX_PRECOND_DIM:
+                        continue
                     self.p[name][d] = np.asarray(st["p"][pp:pp + k * k], np.float64).reshape(k, k)
                     self.q[name][d] = np.asarray(st["q"][pp:pp + k * k], np.float64).reshape(k, k)
                     pp += k * k

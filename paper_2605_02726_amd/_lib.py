@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libcoolchic.so")
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_EDEVICE, CC_ENONFINITE, CC_ESTATE = 0, -1, -2, -3, -4, -5
 CC_SOFT, CC_HARD = 0, 1
 CC_FP32_PLAIN, CC_BF16_FUSED = 0, 1
+CC_OPT_ADAM, CC_OPT_SOAP = 0, 1
 CC_MAX_BATCH = 32
 
 ERRORS = {CC_EINVAL: "EINVAL", CC_ENOMEM: "ENOMEM", CC_EDEVICE: "EDEVICE",
@@ -68,6 +69,12 @@ _PROTOS = [
                                C.c_int64, C.c_void_p]),
     ("cc_get_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cc_set_precision", C.c_int, [C.c_void_p, C.c_int]),
+    ("cc_set_optimizer", C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    ("cc_soap_factor_size", C.c_int64, [C.POINTER(cc_config)]),
+    ("cc_get_soap_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(C.c_int), C.c_void_p]),
+    ("cc_set_soap_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_int, C.c_void_p]),
     ("cc_debug_read", C.c_int, [C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64, C.c_void_p]),
     ("cc_arm_fwd_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                  C.c_void_p, C.c_void_p, C.c_void_p]),

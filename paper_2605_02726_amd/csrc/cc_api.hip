@@ -69,6 +69,8 @@ struct Layout {
          off_dyq, off_dc, off_df, off_U, off_dU, off_X, off_dXa, off_dXb, off_wp, off_wp2,
          off_agt, off_sgt, off_lpb, off_lpm, off_scal, off_aft;
   std::vector<unsigned> arm_gtab, syn_gtab, arm_ftab;
+  std::vector<int> soap_tab;
+  size_t off_stab = 0, off_sm = 0, off_sv = 0, off_sp = 0, off_sq = 0;
   int syn_o[7];
 };
 
@@ -332,6 +334,59 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
     }
   }
 
+  // SOAP table: every decoder-parameter tensor in layout order
+  {
+    struct TT { int poff, nd, dims[4]; };
+    std::vector<TT> ts;
+    const int widths[4] = {h.ctx, h.H1, h.H2, 2};
+    for (int i = 0; i < 3; ++i) {
+      ts.push_back({h.p_aw[i], 2, {widths[i + 1], widths[i], 1, 1}});
+      ts.push_back({h.p_ab[i], 1, {widths[i + 1], 1, 1, 1}});
+    }
+    if (h.arm_stab) {
+      ts.push_back({h.p_asw, 2, {2, h.ctx, 1, 1}});
+      ts.push_back({h.p_asb, 1, {2, 1, 1, 1}});
+    }
+    for (int k = 0; k < h.G; ++k) {
+      ts.push_back({h.p_iw[k], 2, {h.F, h.L - k - 1, 1, 1}});
+      ts.push_back({h.p_ib[k], 1, {h.F, 1, 1, 1}});
+    }
+    for (int j = 1; j < h.L; ++j) ts.push_back({h.p_ups[j], 1, {4, 1, 1, 1}});
+    for (int i = 0; i <= h.n_syn_hidden; ++i) {
+      ts.push_back({h.p_sw[i], 2, {h.syn_w[i + 1], h.syn_w[i], 1, 1}});
+      ts.push_back({h.p_sb[i], 1, {h.syn_w[i + 1], 1, 1, 1}});
+    }
+    if (h.syn_stab) {
+      ts.push_back({h.p_ssw, 2, {3, h.L, 1, 1}});
+      ts.push_back({h.p_ssb, 1, {3, 1, 1, 1}});
+    }
+    for (int r = 0; r < h.n_res; ++r) {
+      ts.push_back({h.p_rw[r], 4, {3, 3, 3, 3}});
+      ts.push_back({h.p_rb[r], 1, {3, 1, 1, 1}});
+    }
+    std::vector<int>& tab = Lo.soap_tab;
+    tab.assign(ts.size() * CC_SOAP_TAB, 0);
+    int fac = 0;
+    for (size_t t = 0; t < ts.size(); ++t) {
+      int* r = &tab[t * CC_SOAP_TAB];
+      int numel = 1;
+      for (int e = 0; e < ts[t].nd; ++e) numel *= ts[t].dims[e];
+      r[0] = ts[t].poff;
+      r[1] = numel;
+      r[2] = ts[t].nd;
+      for (int e = 0; e < 4; ++e) {
+        r[3 + e] = e < ts[t].nd ? ts[t].dims[e] : 1;
+        r[7 + e] = -1;
+        if (ts[t].nd >= 2 && e < ts[t].nd && ts[t].dims[e] <= CC_SOAP_MAXDIM) {
+          r[7 + e] = fac;
+          fac += ts[t].dims[e] * ts[t].dims[e];
+        }
+      }
+    }
+    h.soap_ntens = (int)ts.size();
+    h.soap_nfac = fac;
+  }
+
   // slab layout
   size_t o = 0;
   auto take = [&](size_t n) {
@@ -375,6 +430,11 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   Lo.off_aft = take(sizeof(unsigned) * (size_t)h.n_arm_par);
   Lo.off_lpm = take(sizeof(double) * (size_t)h.pix_ntile);
   Lo.off_scal = take(sizeof(double) * 4);
+  Lo.off_stab = take(sizeof(int) * Lo.soap_tab.size());
+  Lo.off_sm = take(sizeof(float) * (size_t)h.n_par);
+  Lo.off_sv = take(sizeof(float) * (size_t)h.n_par);
+  Lo.off_sp = take(sizeof(float) * (size_t)h.soap_nfac);
+  Lo.off_sq = take(sizeof(float) * (size_t)h.soap_nfac);
   Lo.bytes = o;
 }
 
@@ -404,6 +464,11 @@ void set_pointers(Layout& Lo, char* base) {
   h.lp_bits = (double*)(base + Lo.off_lpb);
   h.lp_mse = (double*)(base + Lo.off_lpm);
   h.scal = (double*)(base + Lo.off_scal);
+  h.soap_tab = (int*)(base + Lo.off_stab);
+  h.soap_m = (float*)(base + Lo.off_sm);
+  h.soap_v = (float*)(base + Lo.off_sv);
+  h.soap_p = (float*)(base + Lo.off_sp);
+  h.soap_q = (float*)(base + Lo.off_sq);
 }
 
 // Seeded default decoder parameters (splitmix64 uniforms).
@@ -448,6 +513,8 @@ struct cc_state {
   int nonfinite;
   int64_t t;
   int device;
+  int optimizer = CC_OPT_ADAM;   // for the decoder parameters
+  int soap_calls = 0;            // SOAP calls made (0: the next one initialises)
 };
 
 namespace {
@@ -611,9 +678,18 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
     }
     // decoder-parameter gradients (with their Adam update) and, in one extra
     // block per image, the loss totals
+    const bool soap = s[0]->optimizer == CC_OPT_SOAP;
     const Launch w1 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, 64) * CC_WRED_SPLIT; });
     const Launch w2 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, CC_ELT_TILE) + 1; });
-    RET(cc_launch_wreduce(w1, w2, update ? 1 : 0, st));
+    RET(cc_launch_wreduce(w1, w2, (update && !soap) ? 1 : 0, st));
+    if (update && soap) {
+      // SOAP on the decoder parameters: one workgroup per parameter tensor
+      SoapPack a;
+      memset(&a, 0, sizeof a);
+      for (int i = 0; i < n; ++i) a.calls[i] = s[i]->soap_calls;
+      RET(cc_launch_soap(plan(s, n, [](const DevDesc& h) { return h.soap_ntens; }), a, st));
+      for (int i = 0; i < n; ++i) ++s[i]->soap_calls;
+    }
     return CC_OK;
   }
   Launch lr;
@@ -728,6 +804,7 @@ int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, doub
   if (e == hipSuccess) e = cp(h.arm_gtab, s->lo.arm_gtab.data(), sizeof(unsigned) * s->lo.arm_gtab.size());
   if (e == hipSuccess) e = cp(h.syn_gtab, s->lo.syn_gtab.data(), sizeof(unsigned) * s->lo.syn_gtab.size());
   if (e == hipSuccess) e = cp(h.arm_ftab, s->lo.arm_ftab.data(), sizeof(unsigned) * s->lo.arm_ftab.size());
+  if (e == hipSuccess) e = cp(h.soap_tab, s->lo.soap_tab.data(), sizeof(int) * s->lo.soap_tab.size());
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete s;
@@ -746,6 +823,7 @@ int cc_encode_step_batch(cc_state* const* states, int n, const cc_step_params* p
     rc = check_params(&p[i]);
     if (rc != CC_OK) return rc;
     if (!same_shape(states[0], states[i])) return fail(CC_EINVAL, "batch mixes decoder shapes or precisions");
+    if (states[i]->optimizer != states[0]->optimizer) return fail(CC_EINVAL, "batch mixes optimisers");
   }
   hipStream_t st = (hipStream_t)stream;
   RET(run_step(states, n, p, st, true, true));
@@ -1023,6 +1101,58 @@ int cc_set_precision(cc_state* s, int precision) {
   h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
   h.prod[h.prod_arm].nrows = h.arm_nwg;
   HIPCHK(hipMemcpy(s->ddev, &h, sizeof(DevDesc), hipMemcpyHostToDevice));
+  return CC_OK;
+}
+
+int cc_set_optimizer(cc_state* s, int optimizer, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  if (optimizer != CC_OPT_ADAM && optimizer != CC_OPT_SOAP) return fail(CC_EINVAL, "optimizer=%d", optimizer);
+  const DevDesc& h = s->lo.h;
+  if (optimizer == CC_OPT_SOAP) {
+    for (int t = 0; t < h.soap_ntens; ++t)
+      if (s->lo.soap_tab[(size_t)t * CC_SOAP_TAB + 1] > CC_SOAP_MAXNUMEL)
+        return fail(CC_EINVAL, "parameter tensor %d has more than %d values", t, CC_SOAP_MAXNUMEL);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemsetAsync(h.soap_m, 0, sizeof(float) * h.n_par, st));
+    HIPCHK(hipMemsetAsync(h.soap_v, 0, sizeof(float) * h.n_par, st));
+    s->soap_calls = 0;
+  }
+  s->optimizer = optimizer;
+  return CC_OK;
+}
+
+int64_t cc_soap_factor_size(const cc_config* cfg) {
+  if (check_config(cfg, 1 << (cfg ? cfg->L - 1 : 0), 1 << (cfg ? cfg->L - 1 : 0)) != CC_OK) return -1;
+  Layout lo;
+  build_layout(cfg, 1 << (cfg->L - 1), 1 << (cfg->L - 1), lo);
+  return lo.h.soap_nfac;
+}
+
+int cc_get_soap_state(cc_state* s, float* m, float* v, float* p, float* q, int* calls, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  if (m) HIPCHK(hipMemcpyAsync(m, h.soap_m, sizeof(float) * h.n_par, hipMemcpyDeviceToHost, st));
+  if (v) HIPCHK(hipMemcpyAsync(v, h.soap_v, sizeof(float) * h.n_par, hipMemcpyDeviceToHost, st));
+  if (p) HIPCHK(hipMemcpyAsync(p, h.soap_p, sizeof(float) * h.soap_nfac, hipMemcpyDeviceToHost, st));
+  if (q) HIPCHK(hipMemcpyAsync(q, h.soap_q, sizeof(float) * h.soap_nfac, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (calls) *calls = s->soap_calls;
+  return CC_OK;
+}
+
+int cc_set_soap_state(cc_state* s, const float* m, const float* v, const float* p, const float* q,
+                      int calls, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  if (calls < 0) return fail(CC_EINVAL, "calls=%d", calls);
+  const DevDesc& h = s->lo.h;
+  hipStream_t st = (hipStream_t)stream;
+  if (m) HIPCHK(hipMemcpyAsync(h.soap_m, m, sizeof(float) * h.n_par, hipMemcpyHostToDevice, st));
+  if (v) HIPCHK(hipMemcpyAsync(h.soap_v, v, sizeof(float) * h.n_par, hipMemcpyHostToDevice, st));
+  if (p) HIPCHK(hipMemcpyAsync(h.soap_p, p, sizeof(float) * h.soap_nfac, hipMemcpyHostToDevice, st));
+  if (q) HIPCHK(hipMemcpyAsync(h.soap_q, q, sizeof(float) * h.soap_nfac, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  s->soap_calls = calls;
   return CC_OK;
 }
 

@@ -40,7 +40,7 @@ struct DevDesc {
   double lambda;
   float rate_scale, mse_scale, lmin, lmax, pmin, bits_max;
   unsigned seed_lo, seed_hi;
-  // ---- per-step scalars (written by the set_step kernel)
+  // ---- per-step scalars (written by the quantiser kernel)
   float T, sr_c, sr_invT, sigma, lr, bc1, bc2;
   unsigned t_lo;
   int mode, upd;
@@ -58,11 +58,18 @@ struct DevDesc {
   int arm_nwg_plain, arm_nwg_fused, arm_fused;  // arm_fused: planes A/B hold the rate gradient
   unsigned* syn_gtab;
   double *lp_bits, *lp_mse, *scal;
+  // ---- SOAP for the decoder parameters (k_soap.hip): one table row of
+  // CC_SOAP_TAB ints per parameter tensor, first and second moments in
+  // parameter order, then every Kronecker factor and every basis (row-major,
+  // tensor by tensor, dimension by dimension)
+  int soap_ntens, soap_nfac;
+  int* soap_tab;
+  float *soap_m, *soap_v, *soap_p, *soap_q;
 };
 
 // Read-only views used inside kernels: the descriptor and the decoder
-// parameters never change during a kernel that reads them (only the Adam and
-// set-step kernels write them, through plain pointers), so they are read in
+// parameters never change during a kernel that reads them (only the
+// optimiser and quantiser kernels write them, through plain pointers), so they are read in
 // the constant address space, which lets uniform reads go through scalar
 // loads (and weights feed FMAs as scalar operands).
 typedef __attribute__((address_space(4))) const struct DevDesc CDesc;
@@ -83,6 +90,10 @@ struct StepArgs {
 };
 struct StepPack {
   StepArgs a[CC_MAX_BATCH];
+};
+// Per image: SOAP calls made before this one (0 = the initialising call).
+struct SoapPack {
+  int calls[CC_MAX_BATCH];
 };
 
 __device__ __forceinline__ int cc_find_img(const Launch& L, int b) {
@@ -108,6 +119,7 @@ int cc_launch_res_bwd(const Launch& l, int r, hipStream_t st);
 int cc_launch_wreduce(const Launch& l1, const Launch& l2, int adam, hipStream_t st);
 int cc_launch_lreduce(const Launch& l, hipStream_t st);
 int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
+int cc_launch_soap(const Launch& l, const SoapPack& a, hipStream_t st);
 
 // Tile geometry shared by host launch planning and kernels.
 #define CC_ELT_TILE 256     // elementwise kernels: threads per block
@@ -119,6 +131,10 @@ int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
 #define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
+#define CC_SOAP_TAB 12       // SOAP table row: poff, numel, ndim, dims[4], factor offsets[4], pad
+#define CC_SOAP_MAXDIM 48    // SOAP: dimensions above this get no Kronecker factor
+#define CC_SOAP_MAXNUMEL 1024  // SOAP: largest parameter tensor
+#define CC_SOAP_REFRESH 10   // SOAP: basis refresh every this many updates
 #define CC_POOL_BLOCK 64    // IFCE gradient pooling: largest base block side (L <= 7)
 #define CC_RES_TH 8         // residual-layer adjoint: tile rows (a multiple of 4)
 #define CC_RES_TW 64        // residual-layer adjoint: tile columns (one per lane)

@@ -63,7 +63,8 @@ class Encoder:
     parameters, Adam moments, scratch) in one slab."""
 
     def __init__(self, mc, image, lam: float, seed: int, latents=None, params=None,
-                 precision: str = "fp32", slab: Optional[torch.Tensor] = None):
+                 precision: str = "fp32", slab: Optional[torch.Tensor] = None,
+                 optimizer: str = "adam"):
         if not torch.cuda.is_available():
             raise RuntimeError("the encode step needs a HIP GPU")
         self.mc = mc
@@ -98,6 +99,9 @@ class Encoder:
         self.handle = h
         self.lam = float(lam)
         self.seed = int(seed)
+        self.optimizer = "adam"
+        if optimizer != "adam":
+            self.set_optimizer(optimizer)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -136,6 +140,33 @@ class Encoder:
     def set_precision(self, precision: str):
         check(lib().cc_set_precision(self.handle, PRECISIONS[precision]))
         self.precision = precision
+
+    def set_optimizer(self, optimizer: str):
+        """Decoder-parameter optimiser: "adam" or "soap" (selecting SOAP
+        clears its state; the next step initialises it)."""
+        kinds = {"adam": _lib.CC_OPT_ADAM, "soap": _lib.CC_OPT_SOAP}
+        check(lib().cc_set_optimizer(self.handle, kinds[optimizer], _stream()))
+        self.optimizer = optimizer
+
+    def soap_factor_size(self) -> int:
+        return int(lib().cc_soap_factor_size(C.byref(self.cfg)))
+
+    def get_soap_state(self):
+        nf = self.soap_factor_size()
+        m = np.empty(self.n_par, np.float32)
+        v = np.empty(self.n_par, np.float32)
+        p = np.empty(nf, np.float32)
+        q = np.empty(nf, np.float32)
+        calls = C.c_int()
+        check(lib().cc_get_soap_state(self.handle, _ptr(m), _ptr(v), _ptr(p), _ptr(q),
+                                      C.byref(calls), _stream()))
+        return dict(m=m, v=v, p=p, q=q, calls=int(calls.value))
+
+    def set_soap_state(self, m=None, v=None, p=None, q=None, calls: int = 0):
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+                for a in (m, v, p, q)]
+        check(lib().cc_set_soap_state(self.handle, *[_ptr(a) for a in arrs], int(calls),
+                                      _stream()))
 
     # ------------------------------------------------------------ state --
     def get_state(self):
