@@ -30,7 +30,14 @@ and the latents with Adam, without stating SOAP's settings.  Readings:
     of 10, refresh every basis: order its columns by the estimated
     eigenvalues diag(Q^T P Q), descending (V is permuted along that dimension
     in the same way), then one power step Q <- qr(P Q) with the diagonal of R
-    made positive.
+    made positive;
+  * that QR is Gram-Schmidt with one re-orthogonalisation pass, column by
+    column; when P Q is rank-deficient the factorisation is not unique and
+    its trailing columns would be set by rounding, so a column whose norm
+    after orthogonalisation is below 1e-5 of its norm before is replaced by
+    the first unit vector e_k, e_(k+1), ... (cyclic) that survives the same
+    orthogonalisation.  For a full-rank, well-conditioned P Q this is the
+    QR with a positive diagonal.
 """
 from __future__ import annotations
 
@@ -87,18 +94,41 @@ def eig_desc(p: np.ndarray) -> np.ndarray:
 
 
 def qr_pos(z: np.ndarray) -> np.ndarray:
-    """Q of the QR factorisation with a non-negative diagonal of R."""
+    """Q of the QR factorisation with a non-negative diagonal of R (library)."""
     q, r = np.linalg.qr(z)
     s = np.sign(np.diag(r))
     s[s == 0] = 1.0
     return q * s[None, :]
 
 
+QR_TOL = 1e-5
+
+
+def qr_gs(z: np.ndarray, tol: float = QR_TOL) -> np.ndarray:
+    """Q of the QR factorisation of a square z: Gram-Schmidt with one
+    re-orthogonalisation pass in column order (R's diagonal positive); a
+    column that falls below tol of its norm is replaced by a unit vector."""
+    n = z.shape[1]
+    q = np.zeros_like(z, dtype=np.float64)
+    for k in range(n):
+        cands = [z[:, k]] + [np.eye(n)[:, (k + i) % n] for i in range(n)]
+        for v0 in cands:
+            v = np.array(v0, dtype=np.float64)
+            n0 = np.linalg.norm(v)
+            for _ in range(2):
+                v = v - q[:, :k] @ (q[:, :k].T @ v)
+            nv = np.linalg.norm(v)
+            if n0 > 0 and nv > tol * n0:
+                break
+        q[:, k] = v / nv
+    return q
+
+
 def refresh(p: np.ndarray, q: np.ndarray, v: np.ndarray, d: int):
     """One basis refresh along dimension d: returns (new Q, permuted V)."""
     est = np.diag(q.T @ p @ q)
     order = np.argsort(-est, kind="stable")
-    return qr_pos(p @ q[:, order]), np.take(v, order, axis=d)
+    return qr_gs(p @ q[:, order]), np.take(v, order, axis=d)
 
 
 class SoapState:

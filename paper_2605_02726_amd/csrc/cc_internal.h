@@ -135,6 +135,7 @@ int cc_launch_soap(const Launch& l, const SoapPack& a, hipStream_t st);
 #define CC_SOAP_MAXDIM 48    // SOAP: dimensions above this get no Kronecker factor
 #define CC_SOAP_MAXNUMEL 1024  // SOAP: largest parameter tensor
 #define CC_SOAP_REFRESH 10   // SOAP: basis refresh every this many updates
+#define CC_SOAP_QR_TOL 1e-5  // SOAP: relative residual below which a refreshed column is replaced
 #define CC_POOL_BLOCK 64    // IFCE gradient pooling: largest base block side (L <= 7)
 #define CC_RES_TH 8         // residual-layer adjoint: tile rows (a multiple of 4)
 #define CC_RES_TW 64        // residual-layer adjoint: tile columns (one per lane)

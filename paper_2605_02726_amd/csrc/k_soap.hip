@@ -20,7 +20,8 @@
 //                eigenvalues diag(Q^T P Q), descending (ties by index),
 //                permute V along d the same way, and take one power step
 //                Q_d <- qr(P_d Q_d) (Gram-Schmidt with one re-orthogonalisation
-//                pass, so R has a positive diagonal).
+//                pass, so R has a positive diagonal; columns that vanish
+//                replaced by unit vectors, see qr_gs).
 #include "cc_internal.h"
 
 #include <math.h>
@@ -30,7 +31,7 @@ namespace {
 constexpr float B1 = 0.95f, B2 = 0.95f, BP = 0.95f, EPS = 1e-8f;
 constexpr int MAXN = CC_SOAP_MAXDIM;
 constexpr int MAXE = CC_SOAP_MAXNUMEL;
-constexpr int NT = 256;
+constexpr int NT = 512;
 
 struct Ten {
   int poff, numel, ndim, dim[4], fac[4];
@@ -49,9 +50,11 @@ __device__ Ten load_ten(const CDesc* d, int t) {
   return T;
 }
 
-__device__ int stride_of(const Ten& T, int dd) {
+__device__ __forceinline__ int stride_of(const Ten& T, int dd) {
   int s = 1;
-  for (int e = dd + 1; e < T.ndim; ++e) s *= T.dim[e];
+#pragma unroll
+  for (int e = 1; e < 4; ++e)
+    if (e > dd && e < T.ndim) s *= T.dim[e];
   return s;
 }
 
@@ -70,42 +73,63 @@ __device__ double block_sum(double v, double* red) {
 __device__ void mode_product(const float* in, float* out, const Ten& T, int dd, const float* Q,
                              bool fwd) {
   const int n = T.dim[dd], st = stride_of(T, dd);
+  // element (r, c) of the operator applied along dd: Q[c][r] forward, Q[r][c] back
+  const int rs = fwd ? 1 : n, cs = fwd ? n : 1;
   for (int i = threadIdx.x; i < T.numel; i += NT) {
     const int id = (i / st) % n;
     const int base = i - id * st;
-    float s = 0.0f;
-    for (int j = 0; j < n; ++j) s += (fwd ? Q[j * n + id] : Q[id * n + j]) * in[base + j * st];
-    out[i] = s;
+    const float* q = Q + id * rs;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int j = 0;
+    for (; j + 3 < n; j += 4) {
+      s0 += q[j * cs] * in[base + j * st];
+      s1 += q[(j + 1) * cs] * in[base + (j + 1) * st];
+      s2 += q[(j + 2) * cs] * in[base + (j + 2) * st];
+      s3 += q[(j + 3) * cs] * in[base + (j + 3) * st];
+    }
+    for (; j < n; ++j) s0 += q[j * cs] * in[base + j * st];
+    out[i] = (s0 + s1) + (s2 + s3);
   }
 }
 
-// Rotates buf (in place via the scratch buffer) along every factored
-// dimension; returns the buffer holding the result.
-__device__ float* rotate(float* buf, float* tmp, float* qs, const CDesc* d, const Ten& T, bool fwd) {
-  for (int dd = 0; dd < T.ndim; ++dd) {
-    if (T.fac[dd] < 0) continue;
-    const int n = T.dim[dd];
-    for (int i = threadIdx.x; i < n * n; i += NT) qs[i] = d->soap_q[T.fac[dd] + i];
+// Rotates src along every factored dimension (bases in qall, at the
+// tensor-local offsets qo), alternating between the scratch buffers a and b;
+// returns the buffer holding the result (src itself if no dimension is
+// factored).  src is not modified.
+__device__ float* rotate(float* src, float* a, float* b, const float* qall, const Ten& T,
+                         bool fwd) {
+  float* cur = src;
+  float* nxt = a;
+  int off = 0;
+  #pragma unroll
+  for (int dd = 0; dd < 4; ++dd) {
+    if (dd >= T.ndim || T.fac[dd] < 0) continue;
+    mode_product(cur, nxt, T, dd, qall + off, fwd);
+    off += T.dim[dd] * T.dim[dd];
     __syncthreads();
-    mode_product(buf, tmp, T, dd, qs, fwd);
-    __syncthreads();
-    float* x = buf;
-    buf = tmp;
-    tmp = x;
+    cur = nxt;
+    nxt = (nxt == a) ? b : a;
   }
-  return buf;
+  return cur;
 }
 
 // G_(d) G_(d)^T (n x n) of the tensor held in g, entry (a, b).
 __device__ float gram_entry(const float* g, const Ten& T, int dd, int a, int b) {
   const int n = T.dim[dd], st = stride_of(T, dd), outer = T.numel / (n * st);
-  float s = 0.0f;
-  for (int o = 0; o < outer; ++o)
-    for (int in = 0; in < st; ++in) {
-      const int base = o * n * st + in;
-      s += g[base + a * st] * g[base + b * st];
-    }
-  return s;
+  const int cnt = outer * st;   // pairs summed: (o, in) in row-major order
+  float s0 = 0.0f, s1 = 0.0f;
+  int e = 0;
+  for (; e + 1 < cnt; e += 2) {
+    const int o0 = e / st, i0 = e - o0 * st, o1 = (e + 1) / st, i1 = e + 1 - o1 * st;
+    const int b0 = o0 * n * st + i0, b1 = o1 * n * st + i1;
+    s0 += g[b0 + a * st] * g[b0 + b * st];
+    s1 += g[b1 + a * st] * g[b1 + b * st];
+  }
+  if (e < cnt) {
+    const int o0 = e / st, i0 = e - o0 * st, b0 = o0 * n * st + i0;
+    s0 += g[b0 + a * st] * g[b0 + b * st];
+  }
+  return s0 + s1;
 }
 
 // Stable descending ranking: order[k] = index of the k-th largest value.
@@ -200,54 +224,71 @@ __device__ void jacobi_eig(double* A, double* Vm, int n, double* wk, int* order,
   __syncthreads();
 }
 
-// Q <- qr(Z) for the n x n matrix Z in A (FP64, columns orthonormalised in
-// place, in order); classical Gram-Schmidt with one re-orthogonalisation
-// pass.  A column that vanishes against the earlier ones is replaced by the
-// unit vector of its index, orthogonalised the same way.
-__device__ void gram_schmidt(double* A, int n, double* wk, double* red) {
+// Q <- qr(Z) for the n x n matrix Z in A (FP64, columns replaced by Q in
+// order): Gram-Schmidt with one re-orthogonalisation pass, so R has a
+// positive diagonal.  A rank-deficient Z has no unique factorisation (its
+// trailing columns would be set by rounding), so a column whose norm after
+// orthogonalisation is below CC_SOAP_QR_TOL of its norm before is replaced
+// by the first unit vector e_k, e_(k+1), ... (cyclic) that survives the same
+// orthogonalisation.  rj, zc: scratch of n doubles each.
+__device__ void qr_gs(double* A, int n, double* rj, double* zc, double* red) {
+  constexpr int GRP = 8;   // threads per dot product
+  const int tid = threadIdx.x, g = tid / GRP, l = tid % GRP;
   for (int k = 0; k < n; ++k) {
-    double n0 = 0.0;
-    for (int a = threadIdx.x; a < n; a += NT) n0 += A[a * n + k] * A[a * n + k];
-    n0 = block_sum(n0, red);
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      if (attempt == 1) {
-        for (int a = threadIdx.x; a < n; a += NT) A[a * n + k] = (a == k) ? 1.0 : 0.0;
-        n0 = 1.0;
-        __syncthreads();
-      }
+    double nv = 0.0;
+    for (int cand = 0; cand <= n; ++cand) {
+      const int e = (k + cand - 1) % n;
+      for (int a = tid; a < n; a += NT) zc[a] = cand == 0 ? A[a * n + k] : (a == e ? 1.0 : 0.0);
+      __syncthreads();
+      double n0 = 0.0;
+      for (int a = tid; a < n; a += NT) n0 += zc[a] * zc[a];
+      n0 = sqrt(block_sum(n0, red));
       for (int pass = 0; pass < 2; ++pass) {
-        for (int j = threadIdx.x; j < k; j += NT) {
+        for (int j = g; j < k; j += NT / GRP) {
           double r = 0.0;
-          for (int a = 0; a < n; ++a) r += A[a * n + j] * A[a * n + k];
-          wk[j] = r;
+          for (int a = l; a < n; a += GRP) r += A[a * n + j] * zc[a];
+          for (int off = GRP / 2; off > 0; off >>= 1) r += __shfl_xor(r, off, GRP);
+          if (l == 0) rj[j] = r;
         }
         __syncthreads();
-        for (int a = threadIdx.x; a < n; a += NT) {
-          double z = A[a * n + k];
-          for (int j = 0; j < k; ++j) z -= wk[j] * A[a * n + j];
-          A[a * n + k] = z;
+        for (int a = g; a < n; a += NT / GRP) {
+          double u = 0.0;
+          for (int j = l; j < k; j += GRP) u += rj[j] * A[a * n + j];
+          for (int off = GRP / 2; off > 0; off >>= 1) u += __shfl_xor(u, off, GRP);
+          if (l == 0) zc[a] -= u;
         }
         __syncthreads();
       }
-      double nn = 0.0;
-      for (int a = threadIdx.x; a < n; a += NT) nn += A[a * n + k] * A[a * n + k];
-      nn = block_sum(nn, red);
-      if (nn > 1e-26 * n0 && nn > 0.0) {
-        const double inv = 1.0 / sqrt(nn);
-        for (int a = threadIdx.x; a < n; a += NT) A[a * n + k] *= inv;
-        __syncthreads();
-        break;
-      }
+      nv = 0.0;
+      for (int a = tid; a < n; a += NT) nv += zc[a] * zc[a];
+      nv = sqrt(block_sum(nv, red));
+      if (n0 > 0.0 && nv > CC_SOAP_QR_TOL * n0) break;
     }
+    for (int a = tid; a < n; a += NT) A[a * n + k] = zc[a] / nv;
+    __syncthreads();
   }
 }
 
 __global__ __launch_bounds__(NT) void k_soap(Launch L, SoapPack A) {
-  __shared__ double dA[MAXN * MAXN], dB[MAXN * MAXN];
-  __shared__ float f0[MAXE], f1[MAXE], f2[MAXE];
-  __shared__ float qs[MAXN * MAXN];
-  __shared__ double wk[MAXN], red[NT / 64];
+  // float work buffers and the FP64 buffers of the basis computations share
+  // storage (never live at the same time)
+  constexpr int UF = 6 * MAXE;
+  constexpr int UD = 2 * MAXN * MAXN;
+  constexpr int UBYTES = (UF * 4 > UD * 8 ? UF * 4 : UD * 8);
+  __shared__ __align__(16) char ubuf[UBYTES];
+  __shared__ float fv[MAXE];
+  __shared__ float qall[2 * MAXN * MAXN], pall[2 * MAXN * MAXN];
+  __shared__ double wk[MAXN], zcol[MAXN], red[NT / 64];
   __shared__ int order[MAXN];
+  float* fg = reinterpret_cast<float*>(ubuf);
+  float* fm = fg + MAXE;
+  float* fth = fm + MAXE;
+  float* w0 = fth + MAXE;
+  float* w1 = w0 + MAXE;
+  float* w2 = w1 + MAXE;
+  double* dA = reinterpret_cast<double*>(ubuf);
+  double* dB = dA + MAXN * MAXN;
+
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
   const int t = blockIdx.x - L.tile0[im];
@@ -258,86 +299,121 @@ __global__ __launch_bounds__(NT) void k_soap(Launch L, SoapPack A) {
   float* theta = d->theta + d->n_lat + T.poff;
   float* M = d->soap_m + T.poff;
   float* V = d->soap_v + T.poff;
-
-  for (int i = tid; i < T.numel; i += NT) f0[i] = grad[i];
-  __syncthreads();
+  // the factors (and bases) of one tensor are contiguous in the state; in
+  // pall / qall they start at 0, dimension by dimension
+  int nf = 0;
+#pragma unroll
+  for (int dd = 0; dd < 4; ++dd)
+    if (dd < T.ndim && T.fac[dd] >= 0) nf += T.dim[dd] * T.dim[dd];
+  int f0 = -1;
+#pragma unroll
+  for (int dd = 0; dd < 4; ++dd)
+    if (dd < T.ndim && T.fac[dd] >= 0 && f0 < 0) f0 = T.fac[dd];
 
   if (calls == 0) {
-    // initialising call: factors and their eigenbases, no update
-    for (int dd = 0; dd < T.ndim; ++dd) {
-      if (T.fac[dd] < 0) continue;
+    // initialising call: factors and their eigenbases, no update (the
+    // gradient is held in fv, outside the storage the FP64 buffers share)
+    for (int i = tid; i < T.numel; i += NT) fv[i] = grad[i];
+    __syncthreads();
+    int off = 0;
+    #pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+      if (dd >= T.ndim || T.fac[dd] < 0) continue;
       const int n = T.dim[dd];
       for (int i = tid; i < n * n; i += NT) {
-        const float p = (1.0f - BP) * gram_entry(f0, T, dd, i / n, i % n);
+        const float p = (1.0f - BP) * gram_entry(fv, T, dd, i / n, i % n);
         d->soap_p[T.fac[dd] + i] = p;
         dA[i] = (double)p;
       }
       __syncthreads();
-      jacobi_eig(dA, dB, n, wk, order, red, qs);
-      for (int i = tid; i < n * n; i += NT) d->soap_q[T.fac[dd] + i] = qs[i];
+      jacobi_eig(dA, dB, n, wk, order, red, qall + off);
+      for (int i = tid; i < n * n; i += NT) d->soap_q[T.fac[dd] + i] = qall[off + i];
       __syncthreads();
+      off += n * n;
     }
     return;
   }
+
+  // everything this tensor needs, in one round of loads
+  for (int i = tid; i < T.numel; i += NT) {
+    fg[i] = grad[i];
+    fm[i] = M[i];
+    fv[i] = V[i];
+    fth[i] = theta[i];
+  }
+  if (f0 >= 0)
+    for (int i = tid; i < nf; i += NT) {
+      qall[i] = d->soap_q[f0 + i];
+      pall[i] = d->soap_p[f0 + i];
+    }
+  __syncthreads();
 
   const int s = calls;
   const double scale =
       (double)d->lr * sqrt(1.0 - pow((double)B2, (double)s)) / (1.0 - pow((double)B1, (double)s));
   // first moment (original coordinates)
   for (int i = tid; i < T.numel; i += NT) {
-    const float m = B1 * M[i] + (1.0f - B1) * f0[i];
+    const float m = B1 * fm[i] + (1.0f - B1) * fg[i];
+    fm[i] = m;
     M[i] = m;
-    f1[i] = m;
   }
   __syncthreads();
   // second moment in the rotated coordinates
-  float* gr = rotate(f0, f2, qs, d, T, true);
+  const float* gr = rotate(fg, w0, w1, qall, T, true);
   for (int i = tid; i < T.numel; i += NT) {
-    const float v = B2 * V[i] + (1.0f - B2) * gr[i] * gr[i];
+    const float v = B2 * fv[i] + (1.0f - B2) * gr[i] * gr[i];
+    fv[i] = v;
     V[i] = v;
-    gr[i] = v;
   }
   __syncthreads();
-  float* freeb = gr == f0 ? f2 : f0;
-  float* mr = rotate(f1, freeb, qs, d, T, true);
-  for (int i = tid; i < T.numel; i += NT) mr[i] = mr[i] / (sqrtf(gr[i]) + EPS);
+  // update: rotate_back(rotate(M) / (sqrt(V) + eps))
+  float* mr = rotate(fm, w0, w1, qall, T, true);
+  for (int i = tid; i < T.numel; i += NT) mr[i] = mr[i] / (sqrtf(fv[i]) + EPS);
   __syncthreads();
-  freeb = mr == f1 ? freeb : f1;
-  float* nb = rotate(mr, freeb, qs, d, T, false);
-  for (int i = tid; i < T.numel; i += NT) theta[i] -= (float)(scale * (double)nb[i]);
-  __syncthreads();
+  float* sa = mr == w0 ? w1 : w0;
+  float* sb = (mr == w2 || sa == w2) ? (mr == w1 || sa == w1 ? w0 : w1) : w2;
+  const float* nb = rotate(mr, sa, sb, qall, T, false);
+  for (int i = tid; i < T.numel; i += NT) theta[i] = fth[i] - (float)(scale * (double)nb[i]);
 
-  // factors with this gradient, and the periodic basis refresh
-  for (int i = tid; i < T.numel; i += NT) f0[i] = grad[i];
-  __syncthreads();
-  for (int dd = 0; dd < T.ndim; ++dd) {
-    if (T.fac[dd] < 0) continue;
-    const int n = T.dim[dd];
-    for (int i = tid; i < n * n; i += NT) {
-      float* p = d->soap_p + T.fac[dd] + i;
-      *p = BP * *p + (1.0f - BP) * gram_entry(f0, T, dd, i / n, i % n);
+  // factors with this gradient
+  {
+    int off = 0;
+    #pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+      if (dd >= T.ndim || T.fac[dd] < 0) continue;
+      const int n = T.dim[dd];
+      for (int i = tid; i < n * n; i += NT) {
+        const float p = BP * pall[off + i] + (1.0f - BP) * gram_entry(fg, T, dd, i / n, i % n);
+        pall[off + i] = p;
+        d->soap_p[T.fac[dd] + i] = p;
+      }
+      off += n * n;
     }
   }
   __syncthreads();
   if (s % CC_SOAP_REFRESH != 0) return;
-  for (int dd = 0; dd < T.ndim; ++dd) {
-    if (T.fac[dd] < 0) continue;
+
+  // periodic basis refresh, dimension by dimension (the FP64 buffers reuse
+  // the float work storage from here on)
+  int off = 0;
+  #pragma unroll
+  for (int dd = 0; dd < 4; ++dd) {
+    if (dd >= T.ndim || T.fac[dd] < 0) continue;
     const int n = T.dim[dd];
-    const float* P = d->soap_p + T.fac[dd];
-    float* Q = d->soap_q + T.fac[dd];
-    for (int i = tid; i < n * n; i += NT) dA[i] = (double)Q[i];
-    __syncthreads();
+    const float* P = pall + off;
+    float* Q = qall + off;
+    off += n * n;
     // W = P Q, estimated eigenvalues diag(Q^T W)
     for (int i = tid; i < n * n; i += NT) {
       const int a = i / n, c = i - a * n;
       double w = 0.0;
-      for (int b = 0; b < n; ++b) w += (double)P[a * n + b] * dA[b * n + c];
+      for (int b = 0; b < n; ++b) w += (double)P[a * n + b] * (double)Q[b * n + c];
       dB[i] = w;
     }
     __syncthreads();
     for (int c = tid; c < n; c += NT) {
       double e = 0.0;
-      for (int a = 0; a < n; ++a) e += dA[a * n + c] * dB[a * n + c];
+      for (int a = 0; a < n; ++a) e += (double)Q[a * n + c] * dB[a * n + c];
       wk[c] = e;
     }
     __syncthreads();
@@ -345,19 +421,22 @@ __global__ __launch_bounds__(NT) void k_soap(Launch L, SoapPack A) {
     __syncthreads();
     // V permuted along dd; Z = P Q[:, order] into dA
     const int st = stride_of(T, dd);
-    for (int i = tid; i < T.numel; i += NT) f0[i] = V[i];
-    __syncthreads();
     for (int i = tid; i < T.numel; i += NT) {
       const int id = (i / st) % n;
-      V[i] = f0[i + (order[id] - id) * st];
+      V[i] = fv[i + (order[id] - id) * st];
     }
     for (int i = tid; i < n * n; i += NT) {
       const int a = i / n, k = i - a * n;
       dA[i] = dB[a * n + order[k]];
     }
     __syncthreads();
-    gram_schmidt(dA, n, wk, red);
-    for (int i = tid; i < n * n; i += NT) Q[i] = (float)dA[i];
+    for (int i = tid; i < T.numel; i += NT) fv[i] = V[i];
+    qr_gs(dA, n, wk, zcol, red);
+    for (int i = tid; i < n * n; i += NT) {
+      const float q = (float)dA[i];
+      Q[i] = q;
+      d->soap_q[T.fac[dd] + i] = q;
+    }
     __syncthreads();
   }
 }

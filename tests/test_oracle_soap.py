@@ -176,3 +176,26 @@ def test_encoder_with_soap_keeps_latent_adam_and_skips_first_parameter_update():
     assert np.array_equal(b.theta[n:], par.astype(np.float64))  # no parameter update yet
     losses = [b.step(t, 1e-2, 0.3, 0.2)[0] for t in range(2, 40)]
     assert losses[-1] < losses[0]
+
+
+def test_gram_schmidt_qr_is_the_library_qr_on_full_rank_input():
+    rng = np.random.default_rng(5)
+    for n in (3, 7, 24):
+        z = rng.normal(size=(n, n)) @ np.diag(np.linspace(1.0, 3.0, n))
+        assert np.allclose(S.qr_gs(z), S.qr_pos(z), atol=1e-10)
+
+
+def test_gram_schmidt_qr_on_rank_deficient_input():
+    """Rank r: the first r columns span the range of z, every column is a
+    unit vector orthogonal to the others, and the replaced columns are the
+    unit vectors' orthogonalised remainders (a fixed rule, not rounding)."""
+    rng = np.random.default_rng(6)
+    n, r = 6, 3
+    z = rng.normal(size=(n, r)) @ rng.normal(size=(r, n))
+    q = S.qr_gs(z)
+    assert np.allclose(q.T @ q, np.eye(n), atol=1e-12)
+    u, _, _ = np.linalg.svd(z)
+    rng_basis = u[:, :r]
+    assert np.allclose(rng_basis @ (rng_basis.T @ q[:, :r]), q[:, :r], atol=1e-10)
+    # the rule is deterministic: scaling z does not change the result
+    assert np.allclose(S.qr_gs(3.0 * z), q, atol=1e-10)
