@@ -131,6 +131,28 @@ int cc_eval_loss(cc_state* s, const cc_step_params* p, double* out3, void* strea
 /* Rate and distortion with hard quantisation, no gradient.  Synchronises. */
 int cc_rd_eval(cc_state* s, cc_rd_result* out, void* stream);
 
+/* Quantisation and transmission rate of the decoder parameters (Section
+ * IV-E).  Submodules a = 0 ARM, 1 synthesis (with the residual layers),
+ * 2 upsampling, 3 IFCE; w = 0 weights, 1 biases.  For every submodule in
+ * that order, each pair of steps (2^-8 ... 2^-1 for the weights and for the
+ * biases) is tried with the submodules before it quantised at their choice
+ * and the ones after it unquantised: the parameters become step * rint(p /
+ * step) (ties to even), the integers v are coded with Exp-Golomb (u = 2v - 1
+ * for v > 0, -2v otherwise; the order 0..11 with the fewest bits per group),
+ * and the pair with the lowest MSE + lambda (R(latents) + R_NN) / (H W),
+ * latents hard-quantised, is kept (the first one on ties).  The state is left
+ * with the chosen quantised decoder parameters.  step_index / step / kappa:
+ * -1 / 0 / -1 for a group without parameters.  Synchronises `stream`. */
+typedef struct cc_nnq_result {
+  int step_index[4][2];   /* e: step 2^(e-8) */
+  double step[4][2];
+  int kappa[4][2];        /* Exp-Golomb order */
+  double nn_bits;         /* R_NN: bits of all parameter codes */
+  double bits, mse, psnr; /* latent bits and distortion with the quantised decoder */
+  double loss;            /* mse + lambda (bits + nn_bits) / (H W) */
+} cc_nnq_result;
+int cc_nn_quantize(cc_state* s, cc_nnq_result* out, void* stream);
+
 /* Decoded image [3, H, W] (hard quantisation -> upsampling -> synthesis)
  * into the caller's device buffer. */
 int cc_decode(cc_state* s, float* out_img_dev, void* stream);

@@ -46,6 +46,12 @@ class cc_rd_result(C.Structure):
                 ("psnr", C.c_double), ("loss", C.c_double)]
 
 
+class cc_nnq_result(C.Structure):
+    _fields_ = [("step_index", (C.c_int * 2) * 4), ("step", (C.c_double * 2) * 4),
+                ("kappa", (C.c_int * 2) * 4), ("nn_bits", C.c_double), ("bits", C.c_double),
+                ("mse", C.c_double), ("psnr", C.c_double), ("loss", C.c_double)]
+
+
 _lib = None
 
 # (name, restype, argtypes)
@@ -62,6 +68,7 @@ _PROTOS = [
                                        C.c_void_p, C.c_void_p]),
     ("cc_eval_loss", C.c_int, [C.c_void_p, C.POINTER(cc_step_params), C.c_void_p, C.c_void_p]),
     ("cc_rd_eval", C.c_int, [C.c_void_p, C.POINTER(cc_rd_result), C.c_void_p]),
+    ("cc_nn_quantize", C.c_int, [C.c_void_p, C.POINTER(cc_nnq_result), C.c_void_p]),
     ("cc_decode", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cc_get_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.POINTER(C.c_int64), C.c_void_p]),

@@ -70,6 +70,8 @@ struct Layout {
          off_agt, off_sgt, off_lpb, off_lpm, off_scal, off_aft;
   std::vector<unsigned> arm_gtab, syn_gtab, arm_ftab;
   std::vector<int> soap_tab;
+  std::vector<unsigned char> nnq_group;
+  size_t off_ngrp = 0, off_nkeep = 0, off_nbits = 0;
   size_t off_stab = 0, off_sm = 0, off_sv = 0, off_sp = 0, off_sq = 0;
   int syn_o[7];
 };
@@ -387,6 +389,43 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
     h.soap_nfac = fac;
   }
 
+  // quantisation groups of the decoder parameters: 2 * submodule + is_bias,
+  // submodules 0 ARM, 1 synthesis (with the residual layers), 2 upsampling,
+  // 3 IFCE
+  {
+    std::vector<unsigned char>& g = Lo.nnq_group;
+    g.assign(h.n_par, 0);
+    auto mark = [&](int beg, int cnt, int grp) {
+      for (int i = 0; i < cnt; ++i) g[beg + i] = (unsigned char)grp;
+    };
+    const int widths[4] = {h.ctx, h.H1, h.H2, 2};
+    for (int i = 0; i < 3; ++i) {
+      mark(h.p_aw[i], widths[i + 1] * widths[i], 0);
+      mark(h.p_ab[i], widths[i + 1], 1);
+    }
+    if (h.arm_stab) {
+      mark(h.p_asw, 2 * h.ctx, 0);
+      mark(h.p_asb, 2, 1);
+    }
+    for (int k = 0; k < h.G; ++k) {
+      mark(h.p_iw[k], h.F * (h.L - k - 1), 6);
+      mark(h.p_ib[k], h.F, 7);
+    }
+    for (int j = 1; j < h.L; ++j) mark(h.p_ups[j], 4, 4);
+    for (int i = 0; i <= h.n_syn_hidden; ++i) {
+      mark(h.p_sw[i], h.syn_w[i + 1] * h.syn_w[i], 2);
+      mark(h.p_sb[i], h.syn_w[i + 1], 3);
+    }
+    if (h.syn_stab) {
+      mark(h.p_ssw, 3 * h.L, 2);
+      mark(h.p_ssb, 3, 3);
+    }
+    for (int r = 0; r < h.n_res; ++r) {
+      mark(h.p_rw[r], 81, 2);
+      mark(h.p_rb[r], 3, 3);
+    }
+  }
+
   // slab layout
   size_t o = 0;
   auto take = [&](size_t n) {
@@ -435,6 +474,9 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   Lo.off_sv = take(sizeof(float) * (size_t)h.n_par);
   Lo.off_sp = take(sizeof(float) * (size_t)h.soap_nfac);
   Lo.off_sq = take(sizeof(float) * (size_t)h.soap_nfac);
+  Lo.off_ngrp = take((size_t)h.n_par);
+  Lo.off_nkeep = take(sizeof(float) * (size_t)h.n_par);
+  Lo.off_nbits = take(sizeof(long long) * CC_NNQ_NG * CC_NNQ_NK);
   Lo.bytes = o;
 }
 
@@ -469,6 +511,9 @@ void set_pointers(Layout& Lo, char* base) {
   h.soap_v = (float*)(base + Lo.off_sv);
   h.soap_p = (float*)(base + Lo.off_sp);
   h.soap_q = (float*)(base + Lo.off_sq);
+  h.nnq_group = (unsigned char*)(base + Lo.off_ngrp);
+  h.nnq_keep = (float*)(base + Lo.off_nkeep);
+  h.nnq_bits = (long long*)(base + Lo.off_nbits);
 }
 
 // Seeded default decoder parameters (splitmix64 uniforms).
@@ -805,6 +850,7 @@ int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, doub
   if (e == hipSuccess) e = cp(h.syn_gtab, s->lo.syn_gtab.data(), sizeof(unsigned) * s->lo.syn_gtab.size());
   if (e == hipSuccess) e = cp(h.arm_ftab, s->lo.arm_ftab.data(), sizeof(unsigned) * s->lo.arm_ftab.size());
   if (e == hipSuccess) e = cp(h.soap_tab, s->lo.soap_tab.data(), sizeof(int) * s->lo.soap_tab.size());
+  if (e == hipSuccess) e = cp(h.nnq_group, s->lo.nnq_group.data(), s->lo.nnq_group.size());
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete s;
@@ -875,6 +921,94 @@ int cc_rd_eval(cc_state* s, cc_rd_result* out, void* stream) {
     out->mse = sc[2];
     out->bpp = sc[1] / hw;
     out->psnr = sc[2] > 0 ? 10.0 * log10(1.0 / sc[2]) : INFINITY;
+  }
+  return CC_OK;
+}
+
+int cc_nn_quantize(cc_state* s, cc_nnq_result* out, void* stream) {
+  RET(check_state(s));
+  hipStream_t st = (hipStream_t)stream;
+  const DevDesc& h = s->lo.h;
+  // keep the unquantised parameters; every candidate is written from them
+  HIPCHK(hipMemcpyAsync(h.nnq_keep, h.theta + h.n_lat, sizeof(float) * h.n_par,
+                        hipMemcpyDeviceToDevice, st));
+  int size[CC_NNQ_NG] = {0};
+  for (int p = 0; p < h.n_par; ++p) ++size[s->lo.nnq_group[p]];
+  Launch l;
+  memset(&l, 0, sizeof l);
+  l.n = 1;
+  l.d[0] = s->ddev;
+  NnqPack pack;
+  long long cnt[CC_NNQ_NG * CC_NNQ_NK];
+  int chosen[4][2];
+  for (int a = 0; a < 4; ++a) chosen[a][0] = chosen[a][1] = -1;
+  const double hw = (double)h.H * h.W;
+  // evaluates the current pack: hard-quantised latents with the decoder of
+  // the pack; returns the cost and fills mse, latent bits and R_NN
+  auto evaluate = [&](double* mse, double* bits, double* nn_bits, int* kap) -> int {
+    RET(cc_launch_nnq(l, pack, st));
+    cc_rd_result r;
+    RET(cc_rd_eval(s, &r, st));
+    HIPCHK(hipMemcpyAsync(cnt, h.nnq_bits, sizeof cnt, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double nb = 0.0;
+    for (int g = 0; g < CC_NNQ_NG; ++g) {
+      if (kap) kap[g] = -1;
+      if (!(pack.step[0][g] > 0.0f) || size[g] == 0) continue;
+      int bk = 0;
+      for (int k = 1; k < CC_NNQ_NK; ++k)
+        if (cnt[g * CC_NNQ_NK + k] < cnt[g * CC_NNQ_NK + bk]) bk = k;
+      nb += (double)cnt[g * CC_NNQ_NK + bk];
+      if (kap) kap[g] = bk;
+    }
+    *mse = r.mse;
+    *bits = r.bits;
+    *nn_bits = nb;
+    return CC_OK;
+  };
+  auto set_pack = [&](int cur, int iw, int ib) {
+    memset(&pack, 0, sizeof pack);
+    for (int a = 0; a < 4; ++a) {
+      const int w = a == cur ? iw : chosen[a][0], b = a == cur ? ib : chosen[a][1];
+      pack.step[0][2 * a] = w >= 0 ? ldexpf(1.0f, w - 8) : 0.0f;
+      pack.step[0][2 * a + 1] = b >= 0 ? ldexpf(1.0f, b - 8) : 0.0f;
+    }
+  };
+  for (int a = 0; a < 4; ++a) {   // ARM, synthesis, upsampling, IFCE
+    if (size[2 * a] == 0 && size[2 * a + 1] == 0) continue;
+    double best = INFINITY;
+    int bw = 0, bb = -1;
+    for (int iw = 0; iw < CC_NNQ_NSTEP; ++iw)
+      for (int ib = size[2 * a + 1] ? 0 : -1; ib < (size[2 * a + 1] ? CC_NNQ_NSTEP : 0); ++ib) {
+        set_pack(a, size[2 * a] ? iw : -1, ib);
+        double mse, bits, nb;
+        RET(evaluate(&mse, &bits, &nb, nullptr));
+        const double cost = mse + h.lambda * (bits + nb) / hw;
+        if (cost < best) {
+          best = cost;
+          bw = size[2 * a] ? iw : -1;
+          bb = ib;
+        }
+      }
+    chosen[a][0] = bw;
+    chosen[a][1] = bb;
+  }
+  set_pack(-1, -1, -1);
+  double mse, bits, nb;
+  int kap[CC_NNQ_NG];
+  RET(evaluate(&mse, &bits, &nb, kap));
+  if (out) {
+    for (int a = 0; a < 4; ++a)
+      for (int w = 0; w < 2; ++w) {
+        out->step_index[a][w] = chosen[a][w];
+        out->step[a][w] = chosen[a][w] >= 0 ? ldexp(1.0, chosen[a][w] - 8) : 0.0;
+        out->kappa[a][w] = kap[2 * a + w];
+      }
+    out->nn_bits = nb;
+    out->bits = bits;
+    out->mse = mse;
+    out->psnr = mse > 0 ? 10.0 * log10(1.0 / mse) : INFINITY;
+    out->loss = mse + h.lambda * (bits + nb) / hw;
   }
   return CC_OK;
 }

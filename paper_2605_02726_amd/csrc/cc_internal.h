@@ -65,6 +65,12 @@ struct DevDesc {
   int soap_ntens, soap_nfac;
   int* soap_tab;
   float *soap_m, *soap_v, *soap_p, *soap_q;
+  // ---- decoder-parameter quantisation (k_nnq.hip): group of every
+  // parameter (2 * submodule + is_bias), the kept unquantised parameters,
+  // Exp-Golomb code lengths per group and order
+  unsigned char* nnq_group;
+  float* nnq_keep;
+  long long* nnq_bits;
 };
 
 // Read-only views used inside kernels: the descriptor and the decoder
@@ -90,6 +96,13 @@ struct StepArgs {
 };
 struct StepPack {
   StepArgs a[CC_MAX_BATCH];
+};
+#define CC_NNQ_NG 8   // parameter groups: 4 submodules x (weights, biases)
+#define CC_NNQ_NK 12  // Exp-Golomb orders 0..11
+#define CC_NNQ_NSTEP 8  // quantisation steps 2^-8 .. 2^-1
+// Per image: quantisation step of every group (0 = unquantised).
+struct NnqPack {
+  float step[CC_MAX_BATCH][CC_NNQ_NG];
 };
 // Per image: SOAP calls made before this one (0 = the initialising call).
 struct SoapPack {
@@ -120,6 +133,7 @@ int cc_launch_wreduce(const Launch& l1, const Launch& l2, int adam, hipStream_t 
 int cc_launch_lreduce(const Launch& l, hipStream_t st);
 int cc_launch_copy_out(const Launch& l, float* out, hipStream_t st);
 int cc_launch_soap(const Launch& l, const SoapPack& a, hipStream_t st);
+int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 
 // Tile geometry shared by host launch planning and kernels.
 #define CC_ELT_TILE 256     // elementwise kernels: threads per block

@@ -132,6 +132,18 @@ class Encoder:
         check(lib().cc_rd_eval(self.handle, C.byref(r), _stream()))
         return dict(bits=r.bits, bpp=r.bpp, mse=r.mse, psnr=r.psnr, loss=r.loss)
 
+    def nn_quantize(self):
+        """Choose the quantisation steps and Exp-Golomb orders of the decoder
+        parameters by rate-distortion cost and leave the state with the
+        quantised decoder (Section IV-E)."""
+        r = _lib.cc_nnq_result()
+        check(lib().cc_nn_quantize(self.handle, C.byref(r), _stream()))
+        subs = ("arm", "syn", "ups", "ifce")
+        return dict(step_index={a: tuple(r.step_index[i]) for i, a in enumerate(subs)},
+                    step={a: tuple(r.step[i]) for i, a in enumerate(subs)},
+                    kappa={a: tuple(r.kappa[i]) for i, a in enumerate(subs)},
+                    nn_bits=r.nn_bits, bits=r.bits, mse=r.mse, psnr=r.psnr, loss=r.loss)
+
     def decode(self) -> torch.Tensor:
         out = torch.empty(3, self.H, self.W, dtype=torch.float32, device="cuda")
         check(lib().cc_decode(self.handle, C.c_void_p(out.data_ptr()), _stream()))
