@@ -57,7 +57,7 @@ def arm_flops_per_step(mc, H, W):
     return tot
 
 
-def measure_step(precision, steps, warmup, timing=True, optimizer="adam"):
+def measure_step(precision, steps, warmup, timing=True, optimizer="adam", nn_quantize=False):
     import ctypes as C
     import numpy as np
     import torch
@@ -93,6 +93,18 @@ def measure_step(precision, steps, warmup, timing=True, optimizer="adam"):
            "loss": loss, "bits": bits, "mse": mse}
     if arm_n.value:
         out["arm_avg_ms"] = arm_ms.value / arm_n.value
+    if nn_quantize:
+        # decoder-parameter quantisation and its rate (Section IV-E) on the
+        # trained state: 8 x 8 step pairs per submodule, one hard-quantised
+        # evaluation each
+        rd0 = enc.rd_eval()
+        t0 = time.perf_counter()
+        q = enc.nn_quantize()
+        out["nn_quantize"] = {"ms": round(1e3 * (time.perf_counter() - t0), 2),
+                              "nn_bits": q["nn_bits"], "step_index": q["step_index"],
+                              "kappa": q["kappa"], "psnr_unquantised": round(rd0["psnr"], 4),
+                              "psnr_quantised": round(q["psnr"], 4),
+                              "latent_bits": round(q["bits"], 1)}
     del enc
     return out
 
@@ -244,7 +256,8 @@ def main():
 
     forms = {}
     for p in (["fp32", "bf16"] if args.precision == "both" else [args.precision]):
-        forms[p] = measure_step(p, args.steps, args.warmup, not args.no_kernel_timing)
+        forms[p] = measure_step(p, args.steps, args.warmup, not args.no_kernel_timing,
+                                nn_quantize=(p == "bf16" and not args.only_step))
     head = "bf16" if "bf16" in forms else "fp32"
     main_f = forms[head]
     if not args.no_soap:

@@ -72,6 +72,25 @@ def config_hop() -> ModelConfig:
                        syn_hidden=[40], syn_stab=1, n_res=2)
 
 
+# Table II presets for images below 10^6 pixels (7 latent grids): inter-feature
+# context F on the 1/1, 1/2, 1/4 grids, spatial context s, two ARM hidden
+# layers of the given width, one 1x1 synthesis hidden layer, the number of
+# 3x3 post-filters; both linear stabilizers.
+PRESETS = {
+    "LOP": dict(F=2, s=6, arm=8, syn=8, res=1),
+    "MOP": dict(F=4, s=10, arm=10, syn=16, res=2),
+    "HOP": dict(F=6, s=14, arm=20, syn=48, res=2),
+    "VHOP": dict(F=6, s=20, arm=26, syn=64, res=2),
+}
+
+
+def config_preset(name: str) -> ModelConfig:
+    p = PRESETS[name]
+    return ModelConfig(L=7, n_spatial=p["s"], n_ifce_feat=p["F"], n_ifce_grids=3,
+                       arm_hidden=[p["arm"], p["arm"]], arm_stab=1,
+                       syn_hidden=[p["syn"]], syn_stab=1, n_res=p["res"])
+
+
 def config_tiny() -> ModelConfig:
     """A small shape with every feature switched on, for brute-force tests."""
     return ModelConfig(L=4, n_spatial=6, n_ifce_feat=2, n_ifce_grids=2,

@@ -77,3 +77,17 @@ def test_state_calls_reject_null(lib):
     rc = L.cc_init_state(C.byref(cfg), 64, 64, None, 1e-3, 1, None, None, None, 0, None,
                          C.byref(out))
     assert rc == lib.CC_EINVAL and not out.value
+
+
+@pytest.mark.parametrize("name", ["LOP", "MOP", "HOP", "VHOP"])
+def test_table2_presets_are_supported(lib, name):
+    """Every decoder preset of Table II is compiled in (parameter counts in
+    the table: 0.5k, 1.0k, 1.9k, 2.7k)."""
+    mc = wl.config_preset(name)
+    cfg = lib.make_config(mc)
+    L = lib.lib()
+    assert L.cc_config_supported(C.byref(cfg), 512, 768) == 1, L.cc_last_error()
+    n = L.cc_n_params(C.byref(cfg))
+    assert n == wl.n_params(mc)
+    target = {"LOP": 500, "MOP": 1000, "HOP": 1900, "VHOP": 2700}[name]
+    assert abs(n - target) <= 0.25 * target
