@@ -124,6 +124,19 @@ int cc_encode_step(cc_state* s, const cc_step_params* p, double* out3, void* str
 int cc_encode_step_batch(cc_state* const* states, int n, const cc_step_params* p,
                          double* out, void* stream);
 
+/* Concurrency of the two branches of an iteration.  The rate branch (ARM
+ * forward and backward, IFCE gradient pooling) and the distortion branch
+ * (upsampling, synthesis and their backward) meet only at the latent-gradient
+ * join (Section IV-A: the loss is a sum of the two terms), so by default the
+ * rate branch runs on a second, library-owned non-blocking stream of the
+ * state's device, forked from `stream` after the quantisation kernel and
+ * joined back into it with events before the join; callers still see one
+ * stream.  Results are bitwise the same either way (no kernel shares an
+ * output with the other branch).  Calls on one device serialise their
+ * launches on a per-device lock.  enable = 0 runs both branches on `stream`
+ * in order.  Process-wide; returns the previous setting (1 or 0). */
+int cc_set_branch_overlap(int enable);
+
 /* Loss of the current state for the iteration's quantisation (noise from
  * p->t), without gradient or update: (loss, bits, mse).  Synchronises. */
 int cc_eval_loss(cc_state* s, const cc_step_params* p, double* out3, void* stream);
@@ -238,10 +251,10 @@ int cc_syn_bwd(cc_state* s, const float* grad_xhat, float* grad_zhat, float* gra
 
 /* Live kernel timing for measurement tools: HIP events are recorded on the
  * launch stream around every launch of one kernel class ("arm", "syn_bwd",
- * "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which also applies
- * the latents' Adam update in an encode step; NULL or "" switches timing off;
- * the upsampling classes time all levels of one step as one span) by the calls
- * that follow.  cc_timing_read waits for those events and returns the summed
+ * "res_bwd", "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which
+ * also applies the latents' Adam update in an encode step; NULL or "" switches
+ * timing off; the upsampling and residual classes time all levels or layers of
+ * one step as one span) by the calls that follow.  cc_timing_read waits for those events and returns the summed
  * duration (ms) and the number of timed launches, then resets the record.
  * Process-wide, not thread-safe. */
 int cc_timing_enable(const char* kernel);

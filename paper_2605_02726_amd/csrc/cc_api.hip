@@ -7,6 +7,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -631,7 +633,7 @@ int quantise(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st)
 
 // Optional live timing of one kernel class with HIP events recorded on the
 // launch stream around each of its launches (see cc_timing_enable).
-enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6 };
+enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_RES_BWD = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6 };
 struct Timing {
   int kind = TK_NONE;
   std::vector<hipEvent_t> ev;   // pairs (start, stop)
@@ -664,8 +666,89 @@ struct TimeScope {
   }
 };
 
+// Second stream per device for the rate branch of a step (ARM and IFCE
+// gradient pooling), which depends on the distortion branch (upsampling,
+// synthesis, residual layers, their backward) only through the latent
+// gradient join: the two branches run concurrently, the rate branch on this
+// stream, forked from and joined back into the caller's stream with events.
+// The stream is non-blocking so that the fork also overlaps when the caller
+// uses the legacy default stream.  Calls on one device take the device's lock
+// for their launches, so concurrent callers never interleave their event
+// pairs.
+struct Side {
+  std::mutex mu;
+  bool tried = false;
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMaxSideDev = 64;
+Side g_side[kMaxSideDev];
+std::atomic<bool> g_overlap{true};
+
+// The device's side stream (created on first use with the device current),
+// or nullptr to run both branches on the caller's stream.  Caller holds mu.
+Side* side_stream(int dev) {
+  Side& sd = g_side[dev];
+  if (!sd.tried) {
+    sd.tried = true;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != dev) {
+      sd.tried = false;
+      return nullptr;
+    }
+    if (hipStreamCreateWithFlags(&sd.st, hipStreamNonBlocking) != hipSuccess) sd.st = nullptr;
+    if (sd.st && (hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
+                  hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess)) {
+      (void)hipStreamDestroy(sd.st);
+      sd.st = nullptr;
+    }
+    // a failed creation leaves HIP's last error set; clear it so that the
+    // next launch check does not report it (the step then runs unforked)
+    if (!sd.st) (void)hipGetLastError();
+  }
+  return sd.st ? &sd : nullptr;
+}
+
+// Fork of the rate branch; the destructor joins it back into the caller's
+// stream if join() was not reached (an error return in between), so the
+// caller's stream never runs ahead of work still queued on the side stream.
+struct Fork {
+  std::unique_lock<std::mutex> lk;
+  Side* sd = nullptr;
+  hipStream_t main;
+  bool joined = false;
+  Fork(int dev, hipStream_t st) : main(st) {
+    if (!g_overlap || dev < 0 || dev >= kMaxSideDev) return;
+    lk = std::unique_lock<std::mutex>(g_side[dev].mu);
+    sd = side_stream(dev);
+  }
+  // stream for the rate branch, ordered after everything queued on main
+  hipStream_t begin() {
+    if (!sd) return main;
+    if (hipEventRecord(sd->fork, main) != hipSuccess ||
+        hipStreamWaitEvent(sd->st, sd->fork, 0) != hipSuccess) {
+      sd = nullptr;
+      return main;
+    }
+    return sd->st;
+  }
+  int join() {
+    if (!sd || joined) return CC_OK;
+    joined = true;
+    HIPCHK(hipEventRecord(sd->join, sd->st));
+    HIPCHK(hipStreamWaitEvent(main, sd->join, 0));
+    return CC_OK;
+  }
+  ~Fork() { (void)join(); }
+};
+
 int arm(cc_state* const* s, int n, int bwd, hipStream_t st) {
-  const Launch l = plan(s, n, [](const DevDesc& h) { return h.arm_nwg; });
+  // the fused kernel's workgroups loop over the bands (at most one workgroup
+  // per compute unit for one image, leaving room on each unit for the
+  // distortion branch running beside it); the plain kernel has one per chunk
+  const Launch l = plan(s, n, [](const DevDesc& h) {
+    return h.arm_fused ? std::min(h.arm_nwg, CC_FUSED_MAXWG) : h.arm_nwg;
+  });
   TimeScope ts(bwd ? TK_ARM : TK_NONE, st);
   if (s[0]->lo.h.arm_fused) return cc_launch_arm_fused(l, s[0]->lo.h, bwd, st);
   return cc_launch_arm_plain(l, s[0]->lo.h, bwd, st);
@@ -692,17 +775,28 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
              bool backward) {
   const DevDesc& h0 = s[0]->lo.h;
   RET(quantise(s, n, p, st));
-  RET(arm(s, n, backward ? 1 : 0, st));
-  if (backward && h0.G > 0) {
-    RET(cc_launch_pool(plan(s, n, pool_blocks), st));
+  // the plain FP32 ARM kernel fills every compute unit with vector work for
+  // longer than the whole distortion branch; sharing the units with it made
+  // the step slower, so only the fused form forks
+  Fork fk(h0.arm_fused ? s[0]->device : -1, st);
+  {
+    // rate branch (a2-a4, a10)
+    const hipStream_t sr = fk.begin();
+    RET(arm(s, n, backward ? 1 : 0, sr));
+    if (backward && h0.G > 0) {
+      RET(cc_launch_pool(plan(s, n, pool_blocks), sr));
+    }
   }
   RET(forward_dist(s, n, 1, st));
   if (backward) {
     const Launch lp = plan(s, n, [](const DevDesc& h) { return h.res_nwg; });
     int src_b = 0;
-    for (int r = h0.n_res - 1; r >= 0; --r) {
-      RET(cc_launch_res_bwd2(lp, r, src_b, st));
-      src_b ^= 1;
+    {
+      TimeScope ts(TK_RES_BWD, st);
+      for (int r = h0.n_res - 1; r >= 0; --r) {
+        RET(cc_launch_res_bwd2(lp, r, src_b, st));
+        src_b ^= 1;
+      }
     }
     {
       TimeScope ts(TK_SYN_BWD, st);
@@ -715,6 +809,7 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
         RET(cc_launch_ups_bwd(l, j, st));
       }
     }
+    RET(fk.join());
     {
       // latent gradients, with the latents' Adam update when updating
       TimeScope ts(TK_JOIN, st);
@@ -737,6 +832,7 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
     }
     return CC_OK;
   }
+  RET(fk.join());
   Launch lr;
   memset(&lr, 0, sizeof lr);
   lr.n = n;
@@ -1290,10 +1386,15 @@ int cc_set_soap_state(cc_state* s, const float* m, const float* v, const float* 
   return CC_OK;
 }
 
+int cc_set_branch_overlap(int enable) {
+  return g_overlap.exchange(enable != 0) ? 1 : 0;
+}
+
 int cc_timing_enable(const char* kernel) {
   int k = TK_NONE;
   if (kernel && !strcmp(kernel, "arm")) k = TK_ARM;
   else if (kernel && !strcmp(kernel, "syn_bwd")) k = TK_SYN_BWD;
+  else if (kernel && !strcmp(kernel, "res_bwd")) k = TK_RES_BWD;
   else if (kernel && !strcmp(kernel, "ups_bwd")) k = TK_UPS_BWD;
   else if (kernel && !strcmp(kernel, "join")) k = TK_JOIN;
   else if (kernel && !strcmp(kernel, "ups_fwd")) k = TK_UPS_FWD;

@@ -140,10 +140,15 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_ARM_CHUNK 64     // ARM kernel: positions per chunk (= threads per block)
 #define CC_ARM_CPW 4        // ARM kernel: chunks per workgroup
 #define CC_SYN_CHUNK 64
+#ifndef CC_SYN_CPW
 #define CC_SYN_CPW 12
+#endif
 #define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
 #define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
+#ifndef CC_FUSED_MAXWG
+#define CC_FUSED_MAXWG 512  // fused ARM kernel: workgroups per image (each takes every n-th band)
+#endif
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
 #define CC_SOAP_TAB 12       // SOAP table row: poff, numel, ndim, dims[4], factor offsets[4], pad
 #define CC_SOAP_MAXDIM 48    // SOAP: dimensions above this get no Kronecker factor
@@ -151,8 +156,12 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_SOAP_REFRESH 10   // SOAP: basis refresh every this many updates
 #define CC_SOAP_QR_TOL 1e-5  // SOAP: relative residual below which a refreshed column is replaced
 #define CC_POOL_BLOCK 64    // IFCE gradient pooling: largest base block side (L <= 7)
+#ifndef CC_RES_TH
 #define CC_RES_TH 8         // residual-layer adjoint: tile rows (a multiple of 4)
+#endif
 #define CC_RES_TW 64        // residual-layer adjoint: tile columns (one per lane)
+#ifndef CC_RES_TPW
 #define CC_RES_TPW 1        // residual-layer adjoint: tiles per workgroup
+#endif
 
 int cc_arm_fused_supported(const DevDesc& h);

@@ -123,7 +123,7 @@ __device__ __forceinline__ f32x16 mfma_tiles(const Tile& G, const Tile& C, int n
 }
 
 template <int S, int F, int H1, int H2>
-__global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
+__global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   constexpr int CTX = S + F;
   static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 + CC_MAX_L - 1 <= 32, "shape");
   __shared__ float ywin[HALO + TH][WR];
@@ -149,27 +149,14 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
   const int wg = blockIdx.x - Lc.tile0[im];
-  int k = 0, band = wg;
-  for (;;) {
-    const int nb = (d->gh[k] + TH - 1) / TH;
-    if (band < nb || k == d->L - 1) break;
-    band -= nb;
-    ++k;
-  }
-  const int h = d->gh[k], w = d->gw[k], nk = h * w;
-  const int y0 = band * TH;
+  const int nwg = Lc.tile0[im + 1] - Lc.tile0[im];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, n = lane & 31, hh = lane >> 5;
   const CF* P = (const CF*)(d->theta + d->n_lat);
-  const CF* W1 = P + d->p_aw[0];
-  const CF* W2 = P + d->p_aw[1];
   const CF* W3 = P + d->p_aw[2];
   const bool stab = d->arm_stab != 0;
-  const bool has_ifce = F > 0 && k < d->G;
-  const int nin = d->L - k - 1;
   const float rs = d->rate_scale;
-  const float* yg = d->yhat + d->goff[k];
 
-  // ---- per-workgroup constants
+  // ---- per-workgroup constants (the same for every band)
   if (tid < 32) {
     const int m = tid;
     vec[0][m] = m < H1 ? P[d->p_ab[0] + m] : 0.0f;
@@ -178,11 +165,6 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
     vec[3][m] = m < H2 ? W3[H2 + m] : 0.0f;
     vec[4][m] = (stab && m < CTX) ? P[d->p_asw + m] : 0.0f;
     vec[5][m] = (stab && m < CTX) ? P[d->p_asw + CTX + m] : 0.0f;
-  }
-  if (tid < 64) {
-    const int f = tid >> 3, q = tid & 7;
-    iw[f][q] = (has_ifce && f < F && q < nin) ? P[d->p_iw[k] + f * nin + q] : 0.0f;
-    if (q == 0) ib[f] = (has_ifce && f < F) ? P[d->p_ib[k] + f] : 0.0f;
   }
   // A operands (weights, split BF16) per lane and K step, kept in LDS:
   // operand (matrix mat, step s) of lane l is wop[mat][s][l] (hi) and
@@ -219,6 +201,30 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   }
   const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
   const float bs0 = stab ? P[d->p_asb] : 0.0f, bs1 = stab ? P[d->p_asb + 1] : 0.0f;
+  int nbt = 0;
+  for (int kk = 0; kk < d->L; ++kk) nbt += (d->gh[kk] + TH - 1) / TH;
+
+  // bands wg, wg + nwg, ... of this image (grid 0's bands first, then grid
+  // 1's, ...); every band writes its own partial row and bits partial, so the
+  // results do not depend on the number of workgroups
+  for (int bidx = wg; bidx < nbt; bidx += nwg) {
+  int k = 0, band = bidx;
+  for (;;) {
+    const int nb = (d->gh[k] + TH - 1) / TH;
+    if (band < nb || k == d->L - 1) break;
+    band -= nb;
+    ++k;
+  }
+  const int h = d->gh[k], w = d->gw[k], nk = h * w;
+  const int y0 = band * TH;
+  const bool has_ifce = F > 0 && k < d->G;
+  const int nin = d->L - k - 1;
+  const float* yg = d->yhat + d->goff[k];
+  if (tid < 64) {
+    const int f = tid >> 3, q = tid & 7;
+    iw[f][q] = (has_ifce && f < F && q < nin) ? P[d->p_iw[k] + f * nin + q] : 0.0f;
+    if (q == 0) ib[f] = (has_ifce && f < F) ? P[d->p_ib[k] + f] : 0.0f;
+  }
 
   f32x16 acc1 = {}, acc2 = {}, acc3 = {};
   double bsum = 0.0;
@@ -484,9 +490,9 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
   if (tid == 0) {
     double s = 0.0;
     for (int q = 0; q < NW; ++q) s += bsh[q];
-    d->lp_bits[wg] = s;
+    d->lp_bits[bidx] = s;
   }
-  if (bwd <= 0) return;
+  if (bwd > 0) {
 
   // ---- weight gradients: fixed-order sum over wavefronts, one partial row
   for (int q = 0; q < NW; ++q) {
@@ -507,12 +513,17 @@ __global__ __launch_bounds__(256) void k_arm_fused(Launch Lc, int bwd) {
     }
     __syncthreads();
   }
-  float* out = d->wp + d->prod[d->prod_arm].off + (size_t)wg * d->n_arm_par;
+  float* out = d->wp + d->prod[d->prod_arm].off + (size_t)bidx * d->n_arm_par;
   for (int p = tid; p < d->n_arm_par; p += NW * 64) {
     const unsigned e = d->arm_ftab[p];
     const int kr = (e >> 16) & 0xFF;
     const int a = (e >> 10) & 3, row = (e >> 5) & 31, col = e & 31;
     out[p] = (kr == 0xFF || kr == k) ? wsum[a][row][col] : 0.0f;
+  }
+  }
+  // LDS of this band (window, accumulators, sums, IFCE weights) is reused
+  // by the next one
+  __syncthreads();
   }
 }
 

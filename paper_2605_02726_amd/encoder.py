@@ -50,6 +50,13 @@ def schedule(t: int, n_iter: int, lr0=1e-2, lr1=1e-5, T0=0.35, T1=0.08, s0=0.22,
     return lr, T0 + (T1 - T0) * a, s0 + (s1 - s0) * a
 
 
+def set_branch_overlap(enable: bool) -> bool:
+    """Run the rate branch of every following step concurrently with the
+    distortion branch (the default) or in order on one stream; returns the
+    previous setting."""
+    return bool(lib().cc_set_branch_overlap(1 if enable else 0))
+
+
 def state_bytes(mc, H: int, W: int, precision: str = "fp32") -> int:
     cfg = _lib.make_config(mc, PRECISIONS[precision])
     n = lib().cc_state_bytes(C.byref(cfg), H, W)
