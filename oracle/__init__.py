@@ -9,6 +9,10 @@ Parity status by function (see the tests under tests/test_oracle_*.py):
                                  closed forms, moments)
   softround, q_train, q_hard     pinned (closed forms, limits, continuity)
   spatial_context, ifce_input    pinned (brute-force loops, causality)
+  hyperlatent grids              pinned (nearest upsampling of the extra IFCE
+                                 inputs, reduction to the model without them
+                                 at zero weights, no distortion gradient,
+                                 central finite differences, all-zero rate)
   arm_mlp                        pinned (special cases, explicit loops)
   laplace_bin_prob, latent_bits  pinned (sum to one, closed forms)
   upsample                       pinned (bicubic interpolation routine,
@@ -22,6 +26,8 @@ Parity status by function (see the tests under tests/test_oracle_*.py):
                                  elementwise Adam for diagonal gradients,
                                  equivariance under orthogonal changes of
                                  basis, refresh as power iteration, einsum)
+  nnq (quantisation, Exp-Golomb) pinned (explicit encoder/decoder, bijection,
+                                 exact grouping, per-choice minimality)
   multi-step trajectories        parity unpinned beyond the per-step pins
 """
 from .coolchic_ref import *  # noqa: F401,F403

@@ -14,8 +14,14 @@ independently there):
     grid;
   * IFCE: one linear layer with bias per grid k < n_ifce_grids; its input is
     the co-located value of every coarser grid j = k+1 .. L-1 after nearest
-    upsampling, i.e. grid j at (y >> (j-k), x >> (j-k)), in ascending j;
-    F inter-feature slots are zero on the other grids;
+    upsampling, i.e. grid j at (y >> (j-k), x >> (j-k)), in ascending j,
+    followed by every hyperlatent grid in the same way; F inter-feature slots
+    are zero on the other grids;
+  * hyperlatent grids (Section III-A.3): n_hyper extra grids of resolutions
+    1/2^b ... 1/2^(b + n_hyper - 1) (b = hyper_first), placed after the L
+    latent grids in the flat pyramid; the ARM codes them like the other grids
+    (spatial context only, no IFCE of their own), the IFCEs take them as
+    inputs, and the upsampling and synthesis never see them;
   * ARM output o = (mu, l) with l the log of the Laplace scale b,
     b = exp(clamp(l, logscale_min, logscale_max)); probability floor p_min;
   * the rate term of the loss is in bits per pixel: loss = MSE + lambda *
@@ -48,9 +54,27 @@ BETA1, BETA2, EPS = 0.9, 0.999, 1e-8
 
 
 # ---------------------------------------------------------------- shapes ----
+def n_hyper(cfg: Dict) -> int:
+    return int(cfg.get("n_hyper", 0))
+
+
+def grid_levels(cfg: Dict):
+    """Resolution level of every grid of the pyramid: the L latent grids
+    0 .. L-1, then the hyperlatent grids b .. b + n_hyper - 1."""
+    b = int(cfg.get("hyper_first", 0))
+    return list(range(cfg["L"])) + [b + i for i in range(n_hyper(cfg))]
+
+
 def grid_shapes(cfg: Dict, H: int, W: int):
-    """Grid k has shape (H / 2^k, W / 2^k) (Section III-A.1, eq. 1)."""
-    return [(H >> k, W >> k) for k in range(cfg["L"])]
+    """A grid of level k has shape (H / 2^k, W / 2^k) (Section III-A.1, eq. 1,
+    and Section III-A.3 for the hyperlatent grids)."""
+    return [(H >> k, W >> k) for k in grid_levels(cfg)]
+
+
+def ifce_inputs(cfg: Dict, k: int) -> int:
+    """Inputs of the IFCE of grid k: the coarser latent grids and the
+    hyperlatent grids."""
+    return cfg["L"] - k - 1 + n_hyper(cfg)
 
 
 def causal_offsets(s: int, radius: int = 8):
@@ -74,7 +98,7 @@ def unpack_params(cfg: Dict, flat) -> Dict[str, torch.Tensor]:
     if cfg["arm_stab"]:
         shapes += [("arm.stab.w", (2, ctx)), ("arm.stab.b", (2,))]
     for k in range(cfg["n_ifce_grids"]):
-        shapes += [(f"ifce.{k}.w", (cfg["n_ifce_feat"], L - k - 1)),
+        shapes += [(f"ifce.{k}.w", (cfg["n_ifce_feat"], ifce_inputs(cfg, k))),
                    (f"ifce.{k}.b", (cfg["n_ifce_feat"],))]
     for j in range(1, L):
         shapes.append((f"ups.{j}", (4,)))
@@ -103,7 +127,8 @@ def n_params(cfg: Dict) -> int:
     widths = [ctx] + list(cfg["arm_hidden"]) + [2]
     n += sum(widths[i] * widths[i + 1] + widths[i + 1] for i in range(len(widths) - 1))
     n += (2 * ctx + 2) if cfg["arm_stab"] else 0
-    n += sum(cfg["n_ifce_feat"] * (L - k - 1) + cfg["n_ifce_feat"] for k in range(cfg["n_ifce_grids"]))
+    n += sum(cfg["n_ifce_feat"] * ifce_inputs(cfg, k) + cfg["n_ifce_feat"]
+             for k in range(cfg["n_ifce_grids"]))
     n += 4 * (L - 1)
     widths = [L] + list(cfg["syn_hidden"]) + [3]
     n += sum(widths[i] * widths[i + 1] + widths[i + 1] for i in range(len(widths) - 1))
@@ -157,15 +182,17 @@ def spatial_context(grid, offsets):
     return torch.stack(cols, dim=1)
 
 
-def ifce_input(grids, k: int):
-    """r_i: co-located values of the coarser grids j = k+1..L-1 after
-    nearest-neighbour upsampling to grid k (Section III-A.2).  [h*w, L-k-1]."""
+def ifce_input(cfg, grids, k: int):
+    """r_i: co-located values of the coarser latent grids j = k+1..L-1, then
+    of the hyperlatent grids, after nearest-neighbour upsampling to grid k
+    (Sections III-A.2, III-A.3).  [h*w, ifce_inputs(cfg, k)]."""
     h, w = grids[k].shape
     ys = torch.arange(h)
     xs = torch.arange(w)
+    levels = grid_levels(cfg)
     cols = []
-    for j in range(k + 1, len(grids)):
-        f = j - k
+    for j in list(range(k + 1, cfg["L"])) + list(range(cfg["L"], len(grids))):
+        f = levels[j] - k
         cols.append(grids[j][(ys >> f)[:, None], (xs >> f)[None, :]].reshape(-1))
     return torch.stack(cols, dim=1)
 
@@ -177,7 +204,7 @@ def arm_context(cfg, P, grids, k: int):
     if F == 0:
         return s
     if k < cfg["n_ifce_grids"]:
-        r = ifce_input(grids, k)
+        r = ifce_input(cfg, grids, k)
         f = r @ P[f"ifce.{k}.w"].T + P[f"ifce.{k}.b"]
     else:
         f = s.new_zeros(s.shape[0], F)

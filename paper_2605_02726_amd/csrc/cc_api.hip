@@ -89,11 +89,24 @@ int pool_blocks(const DevDesc& h) {
   return tot;
 }
 
-// Workgroups (and weight-gradient partial rows) of the upsampling adjoint at
-// level j: one per (channel of T_j, 16x16 tile of grid j).
-int ups_bwd_rows(const DevDesc& h, int j) {
-  return cdiv(h.gh[j], CC_UPS_TILE) * cdiv(h.gw[j], CC_UPS_TILE) * (h.L - j);
+// First upsampling level run by the per-source chain kernels: the levels
+// whose output grid (j - 1) has at most CC_UPS_COARSE positions (sizes fall
+// with j, so these are the levels jc .. L - 1); L when there is none.
+int ups_chain_first(const DevDesc& h) {
+  int jc = h.L;
+  while (jc > 1 && h.gh[jc - 2] * h.gw[jc - 2] <= CC_UPS_COARSE) --jc;
+  return jc;
 }
+
+// Workgroups of the tiled upsampling adjoint at level j: one per (channel of
+// T_j, 16x16 tile of grid j); none for the chain levels.
+int ups_tile_wgs(const DevDesc& h, int j) {
+  return j < h.ups_jc ? cdiv(h.gh[j], CC_UPS_TILE) * cdiv(h.gw[j], CC_UPS_TILE) * (h.L - j) : 0;
+}
+
+// Weight-gradient partial rows of level j: one per tiled workgroup, or one
+// per source grid on the chain levels.
+int ups_bwd_rows(const DevDesc& h, int j) { return j < h.ups_jc ? ups_tile_wgs(h, j) : h.L - j; }
 
 int check_config(const cc_config* c, int H, int W) {
   if (!c) return fail(CC_EINVAL, "config is NULL");
@@ -226,6 +239,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.prod_arm = q;
   h.prod[q++] = {0, h.n_arm_par, h.arm_nwg, 0, wpo};
   wpo += (long long)std::max(h.arm_nwg_plain, h.arm_nwg_fused) * h.n_arm_par;
+  h.ups_jc = ups_chain_first(h);
   h.prod_ups1 = q;
   for (int j = 1; j < h.L; ++j) {
     const int rows = ups_bwd_rows(h, j);
@@ -756,14 +770,37 @@ int arm(cc_state* const* s, int n, int bwd, hipStream_t st) {
 
 // Forward of the distortion branch: upsampling, synthesis, residual layers
 // (+ MSE when want_mse).
+// Upsampling forward (a5): the chain levels first (coarsest), then the tiled
+// levels from coarse to fine.
+int ups_forward(cc_state* const* s, int n, hipStream_t st) {
+  const Launch lc = plan(s, n, [](const DevDesc& h) { return h.L - h.ups_jc; });
+  if (lc.tile0[n] > 0) RET(cc_launch_ups_fwd_chain(lc, st));
+  for (int j = s[0]->lo.h.L - 1; j >= 1; --j) {
+    const Launch l = plan(s, n, [j](const DevDesc& h) {
+      return j < h.ups_jc ? cdiv(h.gh[j - 1] * h.gw[j - 1], CC_PIX_TILE) : 0;
+    });
+    if (l.tile0[n] > 0) RET(cc_launch_ups_fwd(l, j, st));
+  }
+  return CC_OK;
+}
+
+// Upsampling backward (a9): the tiled levels from fine to coarse, then the
+// chain levels.
+int ups_backward(cc_state* const* s, int n, hipStream_t st) {
+  for (int j = 1; j < s[0]->lo.h.L; ++j) {
+    const Launch l = plan(s, n, [j](const DevDesc& h) { return ups_tile_wgs(h, j); });
+    if (l.tile0[n] > 0) RET(cc_launch_ups_bwd(l, j, st));
+  }
+  const Launch lc = plan(s, n, [](const DevDesc& h) { return h.L - h.ups_jc; });
+  if (lc.tile0[n] > 0) RET(cc_launch_ups_bwd_chain(lc, st));
+  return CC_OK;
+}
+
 int forward_dist(cc_state* const* s, int n, int want_mse, hipStream_t st) {
   const DevDesc& h0 = s[0]->lo.h;
   {
     TimeScope ts(TK_UPS_FWD, st);
-    for (int j = h0.L - 1; j >= 1; --j) {
-      const Launch l = plan(s, n, [j](const DevDesc& h) { return cdiv(h.gh[j - 1] * h.gw[j - 1], CC_PIX_TILE); });
-      RET(cc_launch_ups_fwd(l, j, st));
-    }
+    RET(ups_forward(s, n, st));
   }
   const Launch lp = plan(s, n, [](const DevDesc& h) { return h.pix_ntile; });
   RET(cc_launch_syn_fwd_plain(lp, h0, (h0.n_res == 0 && want_mse) ? 1 : 0, st));
@@ -804,10 +841,7 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
     }
     {
       TimeScope ts(TK_UPS_BWD, st);
-      for (int j = 1; j < h0.L; ++j) {
-        const Launch l = plan(s, n, [j](const DevDesc& h) { return ups_bwd_rows(h, j); });
-        RET(cc_launch_ups_bwd(l, j, st));
-      }
+      RET(ups_backward(s, n, st));
     }
     RET(fk.join());
     {
@@ -1234,10 +1268,7 @@ int cc_ups_fwd(cc_state* s, const float* yhat, const float* params, float* zhat,
   const size_t npx = (size_t)h.H * h.W;
   RET(copy_d2d(h.yhat, yhat, sizeof(float) * h.n_lat, st));
   RET(copy_d2d(h.theta + h.n_lat, params, sizeof(float) * h.n_par, st));
-  for (int j = h.L - 1; j >= 1; --j) {
-    const Launch l = plan(one, 1, [j](const DevDesc& x) { return cdiv(x.gh[j - 1] * x.gw[j - 1], CC_PIX_TILE); });
-    RET(cc_launch_ups_fwd(l, j, st));
-  }
+  RET(ups_forward(one, 1, st));
   RET(copy_d2d(zhat, h.yhat, sizeof(float) * npx, st));
   return copy_d2d(zhat + npx, h.U + h.uoff[1], sizeof(float) * (h.L - 1) * npx, st);
 }
@@ -1252,10 +1283,7 @@ int cc_ups_bwd(cc_state* s, const float* grad_zhat, float* grad_yhat, float* gra
   const size_t npx = (size_t)h.H * h.W;
   RET(copy_d2d(h.dyq, grad_zhat, sizeof(float) * npx, st));
   RET(copy_d2d(h.dU + h.uoff[1], grad_zhat + npx, sizeof(float) * (h.L - 1) * npx, st));
-  for (int j = 1; j < h.L; ++j) {
-    const Launch l = plan(one, 1, [j](const DevDesc& x) { return ups_bwd_rows(x, j); });
-    RET(cc_launch_ups_bwd(l, j, st));
-  }
+  RET(ups_backward(one, 1, st));
   if (grad_yhat) RET(copy_d2d(grad_yhat, h.dyq, sizeof(float) * h.n_lat, st));
   if (grad_params) RET(params_grad_out(s, grad_params, h.p_ups[1], h.p_ups[1] + 4 * (h.L - 1), st));
   return CC_OK;

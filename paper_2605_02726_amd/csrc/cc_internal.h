@@ -47,6 +47,7 @@ struct DevDesc {
   // ---- producer geometry
   int arm_nchunk, arm_nwg, syn_nchunk, syn_nwg, pix_nwg, nprod;
   int lat_ntile, pix_ntile, res_nwg;
+  int ups_jc;                   // first upsampling level run by the per-source chain kernels (L: none)
   ProdSeg prod[CC_MAX_PROD];
   int prod_arm, prod_syn, prod_res0, prod_ups1;   // producer indices
   // ---- buffers (device pointers inside the slab)
@@ -125,6 +126,8 @@ int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out = nullp
 int cc_launch_poke(float* p, float v, hipStream_t st);
 int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st);
+int cc_launch_ups_fwd_chain(const Launch& l, hipStream_t st);
+int cc_launch_ups_bwd_chain(const Launch& l, hipStream_t st);
 int cc_launch_syn_fwd(const Launch& l, const DevDesc& h, int final_mse, int precision, hipStream_t st);
 int cc_launch_syn_bwd(const Launch& l, const DevDesc& h, int precision, hipStream_t st);
 int cc_launch_res_fwd(const Launch& l, int r, int last, int want_mse, hipStream_t st);
@@ -150,6 +153,9 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_FUSED_MAXWG 512  // fused ARM kernel: workgroups per image (each takes every n-th band)
 #endif
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
+#define CC_UPS_COARSE 2048  // upsampling levels whose output grid has at most this many positions
+                            // run as one workgroup per source grid, all such levels in LDS
+#define CC_UPS_CHAIN_T 1024 // threads of those workgroups
 #define CC_SOAP_TAB 12       // SOAP table row: poff, numel, ndim, dims[4], factor offsets[4], pad
 #define CC_SOAP_MAXDIM 48    // SOAP: dimensions above this get no Kronecker factor
 #define CC_SOAP_MAXNUMEL 1024  // SOAP: largest parameter tensor

@@ -216,6 +216,187 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
   }
 }
 
+// ------------------------------------------- coarse levels, per source ----
+// Channel c of U_j is source grid j + c upsampled through levels j + c, ...,
+// j, so the sources are independent chains.  The levels from ups_jc up (each
+// output grid at most CC_UPS_COARSE positions) run as one workgroup per
+// source g: the forward takes yhat^(g) through levels g, g-1, ..., ups_jc
+// with every intermediate in LDS (writing each U_j channel for the synthesis
+// and the backward), the backward takes dU_{ups_jc} channel g - ups_jc
+// through levels ups_jc, ..., g down to d yhat^(g) and the tap gradients (one
+// partial row per (level, source)).  Rows then columns, in the same
+// operation order as k_ups_fwd, so the forward values are identical.
+constexpr int CT = CC_UPS_CHAIN_T;
+constexpr int CW = CT / 64;   // wavefronts
+
+// 2-D loops of the chain kernels: rows over the wavefronts, columns over the
+// lanes (no division by a run-time width).
+#define CC_FOR2D(rows, cols, r, c)                                  \
+  for (int r = threadIdx.x >> 6; r < (rows); r += CW)               \
+    for (int c = threadIdx.x & 63; c < (cols); c += 64)
+
+// Rows pass: R[iy][ox] = sum_b w_x,b(ox) * A[iy][ix_b(ox)], for hi x wo.
+__device__ __forceinline__ void rows_pass(const float* h, const float* A, float* R, int hi, int wi,
+                                          int wo) {
+  CC_FOR2D(hi, wo, iy, ox) {
+    int tx[4], ix[4];
+    out_taps(ox, wi, tx, ix);
+    float r = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) r += tapv(h, tx[b]) * A[iy * wi + ix[b]];
+    R[iy * wo + ox] = r;
+  }
+}
+
+// Columns pass: B[oy][x] = sum_a w_y,a(oy) * R[iy_a(oy)][x], for ho x w.
+__device__ __forceinline__ void cols_pass(const float* h, const float* R, float* B, int hi, int ho,
+                                          int w) {
+  CC_FOR2D(ho, w, oy, x) {
+    int ty[4], iy[4];
+    out_taps(oy, hi, ty, iy);
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) s += tapv(h, ty[a]) * R[iy[a] * w + x];
+    B[oy * w + x] = s;
+  }
+}
+
+// Adjoint weights of one axis: wa[i][b] = weight of input i in output
+// 2 i - 3 + b (zero outside the output range).
+__device__ __forceinline__ void adj_weights(const float* h, float (*wa)[8], int n_in, int n_out) {
+  for (int e = threadIdx.x; e < 8 * n_in; e += CT) {
+    const int i = e >> 3, b = e & 7, o = 2 * i - 3 + b;
+    wa[i][b] = (o >= 0 && o < n_out) ? axis_w(h, o, i, n_in) : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(CT) void k_ups_fwd_chain(Launch L) {
+  __shared__ float bufA[CC_UPS_COARSE], bufB[CC_UPS_COARSE], rw[CC_UPS_COARSE / 2];
+  const int im = cc_find_img(L, blockIdx.x);
+  const CDesc* d = (const CDesc*)L.d[im];
+  const int jc = d->ups_jc;
+  const int g = jc + (blockIdx.x - L.tile0[im]);   // source grid
+  float* A = bufA;
+  float* B = bufB;
+  {
+    const float* src = d->yhat + d->goff[g];
+    for (int i = threadIdx.x; i < d->gh[g] * d->gw[g]; i += CT) A[i] = src[i];
+  }
+  for (int j = g; j >= jc; --j) {
+    const int hi = d->gh[j], wi = d->gw[j], ho = d->gh[j - 1], wo = d->gw[j - 1];
+    const CF* hc = (const CF*)(d->theta + d->n_lat + d->p_ups[j]);
+    const float h[4] = {hc[0], hc[1], hc[2], hc[3]};
+    __syncthreads();
+    rows_pass(h, A, rw, hi, wi, wo);
+    __syncthreads();
+    cols_pass(h, rw, B, hi, ho, wo);
+    __syncthreads();
+    float* out = d->U + d->uoff[j] + (size_t)(g - j) * ho * wo;
+    for (int i = threadIdx.x; i < ho * wo; i += CT) out[i] = B[i];
+    float* t = A;
+    A = B;
+    B = t;
+  }
+}
+
+__global__ __launch_bounds__(CT) void k_ups_bwd_chain(Launch L) {
+  __shared__ float bufG[CC_UPS_COARSE], bufD[CC_UPS_COARSE];
+  __shared__ float tin[CC_UPS_COARSE / 4], rc[CC_UPS_COARSE / 2], rf[CC_UPS_COARSE / 2],
+      cf[CC_UPS_COARSE / 2];
+  __shared__ float wxa[CC_UPS_COARSE / 4][8], wya[CC_UPS_COARSE / 4][8];
+  __shared__ float sh[4][CW];
+  const int im = cc_find_img(L, blockIdx.x);
+  const CDesc* d = (const CDesc*)L.d[im];
+  const int jc = d->ups_jc;
+  const int g = jc + (blockIdx.x - L.tile0[im]);   // source grid
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  float* G = bufG;
+  float* D = bufD;
+  {
+    const int ho = d->gh[jc - 1], wo = d->gw[jc - 1];
+    const float* src = d->dU + d->uoff[jc] + (size_t)(g - jc) * ho * wo;
+    for (int i = tid; i < ho * wo; i += CT) G[i] = src[i];
+  }
+  for (int j = jc; j <= g; ++j) {
+    const int hi = d->gh[j], wi = d->gw[j], ho = d->gh[j - 1], wo = d->gw[j - 1];
+    const CF* hc = (const CF*)(d->theta + d->n_lat + d->p_ups[j]);
+    const float h[4] = {hc[0], hc[1], hc[2], hc[3]};
+    {
+      const float* ts = tchan(d, j, g - j);
+      for (int i = tid; i < hi * wi; i += CT) tin[i] = ts[i];
+    }
+    adj_weights(h, wxa, wi, wo);
+    adj_weights(h, wya, hi, ho);
+    __syncthreads();
+    // column adjoint of G: rc[oy][ix] over the outputs ox = 2 ix - 3 + b
+    CC_FOR2D(ho, wi, oy, ix) {
+      float a = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int ox = 2 * ix - 3 + b;
+        a += wxa[ix][b] * G[oy * wo + clampi(ox, 0, wo - 1)];
+      }
+      rc[oy * wi + ix] = a;
+    }
+    rows_pass(h, tin, rf, hi, wi, wo);   // rf[iy][ox]: T through the row taps
+    // cf[oy][ix]: T through the column taps
+    CC_FOR2D(ho, wi, oy, ix) {
+      int ty[4], iy[4];
+      out_taps(oy, hi, ty, iy);
+      float s = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) s += tapv(h, ty[a]) * tin[iy[a] * wi + ix];
+      cf[oy * wi + ix] = s;
+    }
+    __syncthreads();
+    // row adjoint of rc: d T_j channel g - j
+    CC_FOR2D(hi, wi, iy, ix) {
+      float a = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int oy = 2 * iy - 3 + b;
+        a += wya[iy][b] * rc[clampi(oy, 0, ho - 1) * wi + ix];
+      }
+      D[iy * wi + ix] = a;
+      if (j == g) d->dyq[d->goff[g] + iy * wi + ix] = a;
+    }
+    // tap gradients: every output o contributes G[o] times the derivative of
+    // U[o] in each tap, through the row taps (rf) and the column taps (cf)
+    float dh[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    CC_FOR2D(ho, wo, oy, ox) {
+      const float gv = G[oy * wo + ox];
+      int ty[4], iy[4], tx[4], ix[4];
+      out_taps(oy, hi, ty, iy);
+      out_taps(ox, wi, tx, ix);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int qa = ty[a] < 4 ? ty[a] : 7 - ty[a];
+        const int qb = tx[a] < 4 ? tx[a] : 7 - tx[a];
+        const float va = gv * rf[iy[a] * wo + ox];
+        const float vb = gv * cf[oy * wi + ix[a]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dh[q] += (qa == q ? va : 0.0f) + (qb == q ? vb : 0.0f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float s2 = wave_sum(dh[q]);
+      if (ln == 0) sh[q][wv] = s2;
+    }
+    __syncthreads();
+    if (tid < 4) {
+      float s2 = 0.0f;
+      for (int w2 = 0; w2 < CW; ++w2) s2 += sh[tid][w2];
+      const long long pg_off = d->prod[d->prod_ups1 + j - 1].off;
+      d->wp[pg_off + (size_t)(g - j) * 4 + tid] = s2;
+    }
+    float* t = G;
+    G = D;
+    D = t;
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ synthesis ----
 template <int NH, int W1, int W2>
 struct SynShape {
@@ -956,6 +1137,14 @@ int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st) {
 }
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st) {
   hipLaunchKernelGGL(k_ups_bwd, dim3(l.tile0[l.n]), dim3(256), 0, st, l, j);
+  return ok();
+}
+int cc_launch_ups_fwd_chain(const Launch& l, hipStream_t st) {
+  hipLaunchKernelGGL(k_ups_fwd_chain, dim3(l.tile0[l.n]), dim3(CT), 0, st, l);
+  return ok();
+}
+int cc_launch_ups_bwd_chain(const Launch& l, hipStream_t st) {
+  hipLaunchKernelGGL(k_ups_bwd_chain, dim3(l.tile0[l.n]), dim3(CT), 0, st, l);
   return ok();
 }
 int cc_launch_res_fwd(const Launch& l, int r, int last, int want_mse, hipStream_t st) {

@@ -16,7 +16,7 @@ The flat parameter vector follows one documented order (shared interface, see
 
   ARM      for each layer: W [out, in] row-major, then b [out];
            then, with the ARM stabilizer, Ws [2, in], bs [2]
-  IFCE     for grid k = 0 .. n_ifce_grids-1: W [F, L-k-1], b [F]
+  IFCE     for grid k = 0 .. n_ifce_grids-1: W [F, L-k-1 + n_hyper], b [F]
   upsample for level j = 1 .. L-1: the 4 free taps (h0, h1, h2, h3) of the
            symmetric 8-tap kernel (h0 h1 h2 h3 h3 h2 h1 h0)
   synthesis for each 1x1 layer: W [out, in], b [out];
@@ -52,6 +52,8 @@ class ModelConfig:
     logscale_min: float = -4.6
     logscale_max: float = 5.0
     p_min: float = 2.0 ** -16
+    n_hyper: int = 0                # hyperlatent grids, resolutions 1/2^b .. 1/2^(b+n_hyper-1)
+    hyper_first: int = 4            # b
 
     def as_dict(self):
         return asdict(self)
@@ -72,10 +74,11 @@ def config_hop() -> ModelConfig:
                        syn_hidden=[40], syn_stab=1, n_res=2)
 
 
-# Table II presets for images below 10^6 pixels (7 latent grids): inter-feature
-# context F on the 1/1, 1/2, 1/4 grids, spatial context s, two ARM hidden
-# layers of the given width, one 1x1 synthesis hidden layer, the number of
-# 3x3 post-filters; both linear stabilizers.
+# Table II presets for images below 10^6 pixels (7 latent grids, hyperlatent
+# grids 1/16 .. 1/64): inter-feature context F on the 1/1, 1/2, 1/4 grids,
+# spatial context s, two ARM hidden layers of the given width, one 1x1
+# synthesis hidden layer, the number of 3x3 post-filters; both linear
+# stabilizers.
 PRESETS = {
     "LOP": dict(F=2, s=6, arm=8, syn=8, res=1),
     "MOP": dict(F=4, s=10, arm=10, syn=16, res=2),
@@ -84,11 +87,20 @@ PRESETS = {
 }
 
 
-def config_preset(name: str) -> ModelConfig:
+def config_preset(name: str, hyper: bool = True) -> ModelConfig:
     p = PRESETS[name]
     return ModelConfig(L=7, n_spatial=p["s"], n_ifce_feat=p["F"], n_ifce_grids=3,
                        arm_hidden=[p["arm"], p["arm"]], arm_stab=1,
-                       syn_hidden=[p["syn"]], syn_stab=1, n_res=p["res"])
+                       syn_hidden=[p["syn"]], syn_stab=1, n_res=p["res"],
+                       n_hyper=3 if hyper else 0, hyper_first=4)
+
+
+def config_hop_hyper() -> ModelConfig:
+    """The 512x768 workload's decoder with three hyperlatent grids (1/16,
+    1/32, 1/64) feeding the IFCEs."""
+    c = config_hop()
+    c.n_hyper, c.hyper_first = 3, 4
+    return c
 
 
 def config_tiny() -> ModelConfig:
@@ -110,7 +122,7 @@ def param_spec(cfg: ModelConfig):
         spec.append(("arm.stab.w", (2, ctx), ctx))
         spec.append(("arm.stab.b", (2,), ctx))
     for k in range(cfg.n_ifce_grids):
-        nin = cfg.L - k - 1
+        nin = cfg.L - k - 1 + cfg.n_hyper
         spec.append((f"ifce.{k}.w", (cfg.n_ifce_feat, nin), nin))
         spec.append((f"ifce.{k}.b", (cfg.n_ifce_feat,), nin))
     for j in range(1, cfg.L):
@@ -132,8 +144,14 @@ def n_params(cfg: ModelConfig) -> int:
     return sum(int(np.prod(s)) for _, s, _ in param_spec(cfg))
 
 
+def grid_levels(cfg: ModelConfig):
+    """Resolution level of every grid of the flat latent pyramid: the L
+    latent grids, then the hyperlatent grids."""
+    return list(range(cfg.L)) + [cfg.hyper_first + i for i in range(cfg.n_hyper)]
+
+
 def n_latents(cfg: ModelConfig, H: int, W: int) -> int:
-    return sum((H >> k) * (W >> k) for k in range(cfg.L))
+    return sum((H >> k) * (W >> k) for k in grid_levels(cfg))
 
 
 def init_params(cfg: ModelConfig, seed: int, arm_out_zero: bool = True,

@@ -50,7 +50,7 @@ def test_ifce_input_is_nearest_upsampling_of_coarser_grids():
     cfg = wl.config_tiny().as_dict()
     grids = _rand_grids(cfg, 16, 24, 1)
     for k in range(cfg["L"] - 1):
-        r = R.ifce_input(grids, k)
+        r = R.ifce_input(cfg, grids, k)
         h, w = grids[k].shape
         for col, j in enumerate(range(k + 1, cfg["L"])):
             up = Fnn.interpolate(grids[j][None, None], size=(h, w), mode="nearest")[0, 0]
