@@ -75,6 +75,15 @@ typedef struct cc_config {
   float logscale_max;
   float p_min;        /* floor of a latent's probability                     */
   int precision;      /* CC_FP32_PLAIN or CC_BF16_FUSED                      */
+  /* Hyperlatent grids (Section III-A.3): n_hyper extra grids of resolutions
+   * 1/2^b .. 1/2^(b + n_hyper - 1), b = hyper_first, stored after the L
+   * latent grids in every flat latent array.  The ARM codes them with their
+   * spatial context (no IFCE of their own), every IFCE takes them as inputs
+   * after the coarser latent grids (nearest upsampling), and the upsampling
+   * and synthesis never see them.  0..4 grids; n_ifce_grids <= b and
+   * b + n_hyper <= L (each resolution is one of the latent grids'). */
+  int n_hyper;
+  int hyper_first;
 } cc_config;
 
 /* Per-iteration scalars (Table I schedules are evaluated by the caller). */

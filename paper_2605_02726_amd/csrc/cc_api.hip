@@ -128,6 +128,14 @@ int check_config(const cc_config* c, int H, int W) {
   if (c->n_res < 0 || c->n_res > 4) return fail(CC_EINVAL, "n_res=%d outside [0, 4]", c->n_res);
   if (c->n_ifce_feat > 0 && (1 << (c->L - 1)) > CC_POOL_BLOCK)
     return fail(CC_EINVAL, "IFCE needs L <= 7 (L=%d)", c->L);
+  if (c->n_hyper < 0 || c->n_hyper > 4) return fail(CC_EINVAL, "n_hyper=%d outside [0, 4]", c->n_hyper);
+  if (c->n_hyper > 0 && (c->hyper_first < 1 || c->hyper_first < c->n_ifce_grids ||
+                         c->hyper_first + c->n_hyper > c->L))
+    return fail(CC_EINVAL, "hyperlatent grids from 1/2^%d (%d of them) need n_ifce_grids <= first and first + n <= L",
+                c->hyper_first, c->n_hyper);
+  if (c->L + c->n_hyper > CC_MAX_G) return fail(CC_EINVAL, "too many grids");
+  if (c->n_ifce_grids > 0 && c->L - 1 + c->n_hyper > CC_MAX_NIN)
+    return fail(CC_EINVAL, "an IFCE would have more than %d inputs", CC_MAX_NIN);
   if (!(c->logscale_min < c->logscale_max)) return fail(CC_EINVAL, "log-scale clamp");
   if (!(c->p_min > 0.0f && c->p_min < 1.0f)) return fail(CC_EINVAL, "p_min must be in (0, 1)");
   if (c->precision != CC_FP32_PLAIN && c->precision != CC_BF16_FUSED)
@@ -154,14 +162,31 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.syn_w[0] = c->L;
   for (int i = 0; i < c->n_syn_hidden; ++i) h.syn_w[1 + i] = c->syn_hidden[i];
   h.syn_w[1 + c->n_syn_hidden] = 3;
+  // flat latent pyramid: latent grids 0 .. L-1, then the hyperlatent grids
+  h.n_hyper = c->n_hyper;
+  h.hyper_first = c->n_hyper > 0 ? c->hyper_first : 0;
+  h.NG = c->L + c->n_hyper;
   int off = 0;
-  for (int k = 0; k < c->L; ++k) {
-    h.gh[k] = H >> k;
-    h.gw[k] = W >> k;
+  for (int k = 0; k < h.NG; ++k) {
+    const int lev = k < c->L ? k : c->hyper_first + (k - c->L);
+    h.glev[k] = lev;
+    h.gh[k] = H >> lev;
+    h.gw[k] = W >> lev;
     h.goff[k] = off;
     off += h.gh[k] * h.gw[k];
   }
   h.n_lat = off;
+  // IFCE inputs of grid k: the coarser latent grids, then the hyperlatent
+  // grids, each at its resolution shift from grid k
+  for (int k = 0; k < h.G; ++k) {
+    int q = 0;
+    for (int j = k + 1; j < h.NG; ++j) {
+      h.isrc[k][q] = j;
+      h.ish[k][q] = h.glev[j] - k;
+      ++q;
+    }
+    h.nin[k] = q;
+  }
   causal_offsets(h.S, h.dy, h.dx);
 
   // decoder parameter offsets in the documented order
@@ -182,7 +207,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   }
   for (int k = 0; k < h.G; ++k) {
     h.p_iw[k] = p;
-    p += h.F * (h.L - k - 1);
+    p += h.F * h.nin[k];
     h.p_ib[k] = p;
     p += h.F;
   }
@@ -221,10 +246,10 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.bits_max = (float)(-log2((double)c->p_min));
 
   // producer geometry
-  for (int k = 0; k < h.L; ++k) h.arm_nchunk += cdiv(h.gh[k] * h.gw[k], CC_ARM_CHUNK);
+  for (int k = 0; k < h.NG; ++k) h.arm_nchunk += cdiv(h.gh[k] * h.gw[k], CC_ARM_CHUNK);
   h.arm_nwg_plain = cdiv(h.arm_nchunk, CC_ARM_CPW);
   h.arm_nwg_fused = 0;
-  for (int k = 0; k < h.L; ++k) h.arm_nwg_fused += cdiv(h.gh[k], CC_FUSED_BAND);
+  for (int k = 0; k < h.NG; ++k) h.arm_nwg_fused += cdiv(h.gh[k], CC_FUSED_BAND);
   h.arm_fused = (c->precision == CC_BF16_FUSED && cc_arm_fused_supported(h)) ? 1 : 0;
   // partial rows are sized for either form; the current one is selected below
   h.arm_nwg = std::max(h.arm_nwg_plain, h.arm_nwg_fused);
@@ -263,7 +288,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   // activation vector, grid requirement) per parameter, matching the LDS row
   // layouts of the ARM and synthesis backward kernels.
   {
-    const int CTX = h.ctx, RM = CC_MAX_L - 1;
+    const int CTX = h.ctx, RM = CC_MAX_NIN;
     const int O_H1 = CTX, O_H2 = O_H1 + h.H1, O_R = O_H2 + h.H2, O_DH1 = O_R + RM,
               O_DH2 = O_DH1 + h.H1, O_DO = O_DH2 + h.H2, O_DF = O_DO + 2, O_ONE = O_DF + h.F;
     auto ent = [](int a, int b, int k) {
@@ -286,7 +311,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
       for (int a = 0; a < 2; ++a) t[h.p_asb + a] = ent(O_DO + a, O_ONE, 0xFF);
     }
     for (int k = 0; k < h.G; ++k) {
-      const int nin = h.L - k - 1;
+      const int nin = h.nin[k];
       for (int f = 0; f < h.F; ++f)
         for (int qq = 0; qq < nin; ++qq) t[h.p_iw[k] + f * nin + qq] = ent(O_DF + f, O_R + qq, k);
       for (int f = 0; f < h.F; ++f) t[h.p_ib[k] + f] = ent(O_DF + f, O_ONE, k);
@@ -316,10 +341,17 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
         t[h.p_asb + a] = ent(0xFF, 0, h.H1 + a, CTX);
       }
     }
+    // IFCE weights: inputs q < Q3 pair the context-gradient rows 2 + f of
+    // the output tile with the input columns H2 + 1 + q of the last hidden
+    // tile; the rest use the spare rows H2 + f and columns H1 + 1 + q - Q3
+    // of the second layer's tiles
+    const int Q3 = 32 - h.H2 - 1;
     for (int k = 0; k < h.G; ++k) {
-      const int nin = h.L - k - 1;
+      const int nin = h.nin[k];
       for (int f = 0; f < h.F; ++f) {
-        for (int q2 = 0; q2 < nin; ++q2) t[h.p_iw[k] + f * nin + q2] = ent(k, 2, 2 + f, h.H2 + 1 + q2);
+        for (int q2 = 0; q2 < nin; ++q2)
+          t[h.p_iw[k] + f * nin + q2] = q2 < Q3 ? ent(k, 2, 2 + f, h.H2 + 1 + q2)
+                                                : ent(k, 1, h.H2 + f, h.H1 + 1 + q2 - Q3);
         t[h.p_ib[k] + f] = ent(k, 2, 2 + f, h.H2);
       }
     }
@@ -366,7 +398,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
       ts.push_back({h.p_asb, 1, {2, 1, 1, 1}});
     }
     for (int k = 0; k < h.G; ++k) {
-      ts.push_back({h.p_iw[k], 2, {h.F, h.L - k - 1, 1, 1}});
+      ts.push_back({h.p_iw[k], 2, {h.F, h.nin[k], 1, 1}});
       ts.push_back({h.p_ib[k], 1, {h.F, 1, 1, 1}});
     }
     for (int j = 1; j < h.L; ++j) ts.push_back({h.p_ups[j], 1, {4, 1, 1, 1}});
@@ -424,7 +456,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
       mark(h.p_asb, 2, 1);
     }
     for (int k = 0; k < h.G; ++k) {
-      mark(h.p_iw[k], h.F * (h.L - k - 1), 6);
+      mark(h.p_iw[k], h.F * h.nin[k], 6);
       mark(h.p_ib[k], h.F, 7);
     }
     for (int j = 1; j < h.L; ++j) mark(h.p_ups[j], 4, 4);
@@ -553,7 +585,7 @@ void default_params(const DevDesc& h, uint64_t seed, std::vector<float>& P) {
   };
   fill(h.p_aw[0], h.H1 * h.ctx + h.H1, h.ctx);
   fill(h.p_aw[1], h.H2 * h.H1 + h.H2, h.H1);
-  for (int k = 0; k < h.G; ++k) fill(h.p_iw[k], h.F * (h.L - k - 1) + h.F, h.L - k - 1);
+  for (int k = 0; k < h.G; ++k) fill(h.p_iw[k], h.F * h.nin[k] + h.F, h.nin[k]);
   const float bic[4] = {-0.03515625f, -0.10546875f, 0.26171875f, 0.87890625f};
   for (int j = 1; j < h.L; ++j)
     for (int t = 0; t < 4; ++t) P[h.p_ups[j] + t] = bic[t];
@@ -598,7 +630,7 @@ Launch plan(cc_state* const* s, int n, F count) {
 
 bool same_shape(const cc_state* a, const cc_state* b) {
   const DevDesc &x = a->lo.h, &y = b->lo.h;
-  return x.L == y.L && x.S == y.S && x.F == y.F && x.G == y.G && x.H1 == y.H1 && x.H2 == y.H2 &&
+  return x.L == y.L && x.NG == y.NG && x.hyper_first == y.hyper_first && x.S == y.S && x.F == y.F && x.G == y.G && x.H1 == y.H1 && x.H2 == y.H2 &&
          x.n_syn_hidden == y.n_syn_hidden && x.syn_w[1] == y.syn_w[1] &&
          x.syn_w[2] == y.syn_w[2] && x.n_res == y.n_res && a->precision == b->precision;
 }
@@ -908,8 +940,10 @@ int cc_config_supported(const cc_config* cfg, int H, int W) { return check_confi
 
 int64_t cc_n_latents(const cc_config* cfg, int H, int W) {
   if (!cfg || cfg->L < 1 || cfg->L > CC_MAX_L) return -1;
+  if (cfg->n_hyper < 0 || cfg->L + cfg->n_hyper > CC_MAX_G) return -1;
   int64_t n = 0;
   for (int k = 0; k < cfg->L; ++k) n += (int64_t)(H >> k) * (W >> k);
+  for (int k = 0; k < cfg->n_hyper; ++k) n += (int64_t)(H >> (cfg->hyper_first + k)) * (W >> (cfg->hyper_first + k));
   return n;
 }
 

@@ -7,7 +7,9 @@
 
 #include "../../include/coolchic.h"
 
-#define CC_MAX_L 8
+#define CC_MAX_L 8    // latent grids
+#define CC_MAX_G 12   // grids of the flat latent pyramid (latent + hyperlatent)
+#define CC_MAX_NIN 10 // inputs of one IFCE (coarser latent grids + hyperlatent grids)
 #define CC_MAX_S 32
 #define CC_MAX_PROD 16
 
@@ -28,7 +30,11 @@ struct DevDesc {
   int H, W, L, S, F, G, H1, H2, ctx, arm_stab, syn_stab, n_syn_hidden, n_res;
   int syn_w[4];                 // L, hidden..., 3 (n_syn_hidden + 2 entries)
   int n_lat, n_par, n_theta;
-  int goff[CC_MAX_L], gh[CC_MAX_L], gw[CC_MAX_L];
+  // flat latent pyramid: the L latent grids, then n_hyper hyperlatent grids
+  int NG, n_hyper, hyper_first;
+  int goff[CC_MAX_G], gh[CC_MAX_G], gw[CC_MAX_G], glev[CC_MAX_G];  // glev: resolution level
+  // IFCE of grid k < G: its inputs (pyramid grid, resolution shift)
+  int nin[4], isrc[4][CC_MAX_NIN], ish[4][CC_MAX_NIN];
   int uoff[CC_MAX_L];           // U_j (j >= 1): (L-j) channels at grid j-1
   int dfoff[4][CC_MAX_L];       // IFCE df pyramid of child grid c at level f
   int dy[CC_MAX_S], dx[CC_MAX_S];

@@ -48,12 +48,12 @@ __device__ __forceinline__ void laplace_bits(float dd, float ib, float& bits, fl
 template <int S, int F, int H1, int H2, bool BWD>
 __global__ __launch_bounds__(64) void k_arm_plain(Launch Lc) {
   constexpr int CTX = S + F;
-  constexpr int RM = CC_MAX_L - 1;
+  constexpr int RM = CC_MAX_NIN;
   constexpr int O_H1 = CTX, O_H2 = O_H1 + H1, O_R = O_H2 + H2, O_DH1 = O_R + RM,
                 O_DH2 = O_DH1 + H1, O_DO = O_DH2 + H2, O_DF = O_DO + 2, O_ONE = O_DF + F;
   constexpr int AST = (O_ONE + 1) | 1;
   constexpr int PMAX = (CTX + 1) * H1 + (H1 + 1) * H2 + (H2 + 1) * 2 + (CTX + 1) * 2 +
-                       3 * F * CC_MAX_L;
+                       3 * F * (CC_MAX_NIN + 1);
   constexpr int NQ = (PMAX + 63) / 64;
   __shared__ float lds[BWD ? 64 * AST : 1];
 
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64) void k_arm_plain(Launch Lc) {
     int k = 0, c0 = ch;
     for (;;) {
       const int nck = (d->gh[k] * d->gw[k] + 63) >> 6;
-      if (c0 < nck || k == d->L - 1) break;
+      if (c0 < nck || k == d->NG - 1) break;
       c0 -= nck;
       ++k;
     }
@@ -113,12 +113,12 @@ __global__ __launch_bounds__(64) void k_arm_plain(Launch Lc) {
 #pragma unroll
       for (int f = 0; f < F; ++f) c[S + f] = 0.0f;
       if (has_ifce) {
-        const int nin = d->L - k - 1;
+        const int nin = d->nin[k];
 #pragma unroll
         for (int q = 0; q < RM; ++q) {
           if (q < nin && valid) {
-            const int j = k + 1 + q;
-            r[q] = d->yhat[d->goff[j] + (y >> (q + 1)) * d->gw[j] + (x >> (q + 1))];
+            const int j = d->isrc[k][q], sh = d->ish[k][q];
+            r[q] = d->yhat[d->goff[j] + (y >> sh) * d->gw[j] + (x >> sh)];
           }
         }
         const CF* Wi = P + d->p_iw[k];

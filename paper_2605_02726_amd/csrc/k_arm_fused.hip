@@ -125,7 +125,12 @@ __device__ __forceinline__ f32x16 mfma_tiles(const Tile& G, const Tile& C, int n
 template <int S, int F, int H1, int H2>
 __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   constexpr int CTX = S + F;
-  static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 + CC_MAX_L - 1 <= 32, "shape");
+  static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 <= 32, "shape");
+  // IFCE inputs q < Q3 go to the columns H2 + 1 + q of the last hidden
+  // tile, the others to the spare columns H1 + 1 + q - Q3 of the second
+  // layer's tile, paired with the context-gradient rows H2 + f there (the
+  // host checks that they fit)
+  constexpr int Q3 = 32 - H2 - 1;
   __shared__ float ywin[HALO + TH][WR];
   // context-gradient accumulators: one private window per wavefront (its 32
   // columns plus HALO on each side, the band rows plus HALO above), merged
@@ -140,9 +145,9 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   Tile(*tc)[NW] = reinterpret_cast<Tile(*)[NW]>(tiles_raw + 3 * NW * sizeof(Tile));
   float(*wsum)[32][33] = reinterpret_cast<float(*)[32][33]>(tiles_raw);
   static_assert(3 * 32 * 33 * sizeof(float) <= 2 * 3 * NW * sizeof(Tile), "wsum alias");
-  __shared__ float pwin[CC_MAX_L - 1][SW / 2 + 1];   // IFCE parents of the segment
+  __shared__ float pwin[CC_MAX_NIN][SW / 2 + 1];   // IFCE inputs of the segment
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
-  __shared__ float iw[8][8], ib[8];  // IFCE weights [feature][input] (zero padded), biases
+  __shared__ float iw[8][CC_MAX_NIN], ib[8];  // IFCE weights [feature][input] (zero padded), biases
   __shared__ double bsh[NW];
   __shared__ bf16x8 wop[4][2][64], wopl[4][2][64];
 
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
   const float bs0 = stab ? P[d->p_asb] : 0.0f, bs1 = stab ? P[d->p_asb + 1] : 0.0f;
   int nbt = 0;
-  for (int kk = 0; kk < d->L; ++kk) nbt += (d->gh[kk] + TH - 1) / TH;
+  for (int kk = 0; kk < d->NG; ++kk) nbt += (d->gh[kk] + TH - 1) / TH;
 
   // bands wg, wg + nwg, ... of this image (grid 0's bands first, then grid
   // 1's, ...); every band writes its own partial row and bits partial, so the
@@ -211,20 +216,25 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   int k = 0, band = bidx;
   for (;;) {
     const int nb = (d->gh[k] + TH - 1) / TH;
-    if (band < nb || k == d->L - 1) break;
+    if (band < nb || k == d->NG - 1) break;
     band -= nb;
     ++k;
   }
   const int h = d->gh[k], w = d->gw[k], nk = h * w;
   const int y0 = band * TH;
   const bool has_ifce = F > 0 && k < d->G;
-  const int nin = d->L - k - 1;
+  const int nin = has_ifce ? d->nin[k] : 0;
+  const bool ifce_extra = nin > Q3;   // some inputs use the second layer's tiles
   const float* yg = d->yhat + d->goff[k];
-  if (tid < 64) {
-    const int f = tid >> 3, q = tid & 7;
+  if (tid < 8 * CC_MAX_NIN) {
+    const int f = tid / CC_MAX_NIN, q = tid - f * CC_MAX_NIN;
     iw[f][q] = (has_ifce && f < F && q < nin) ? P[d->p_iw[k] + f * nin + q] : 0.0f;
     if (q == 0) ib[f] = (has_ifce && f < F) ? P[d->p_ib[k] + f] : 0.0f;
   }
+  // resolution shift of every IFCE input (uniform)
+  int shq[CC_MAX_NIN];
+#pragma unroll
+  for (int q = 0; q < CC_MAX_NIN; ++q) shq[q] = q < nin ? d->ish[k][q] : 1;
 
   f32x16 acc1 = {}, acc2 = {}, acc3 = {};
   double bsum = 0.0;
@@ -240,13 +250,14 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       const int gy = y0 - HALO + r, gx = x0 - HALO + c;
       (&ywin[0][0])[i] = (gy >= 0 && gy < h && gx >= 0 && gx < w) ? yg[gy * w + gx] : 0.0f;
     }
-    // parents of the band (y0 is even: both rows share each coarser row)
+    // IFCE inputs of the band: every input grid is coarser (shift >= 1)
+    // and y0 is even, so both rows share each input row
     if (has_ifce) {
-      for (int i = tid; i < (CC_MAX_L - 1) * (SW / 2 + 1); i += NW * 64) {
+      for (int i = tid; i < CC_MAX_NIN * (SW / 2 + 1); i += NW * 64) {
         const int q = i / (SW / 2 + 1), c = i - q * (SW / 2 + 1);
         if (q < nin) {
-          const int j = k + 1 + q;
-          const int py = y0 >> (q + 1), px = (x0 >> (q + 1)) + c;
+          const int j = d->isrc[k][q], sh = d->ish[k][q];
+          const int py = y0 >> sh, px = (x0 >> sh) + c;
           pwin[q][c] = (py < d->gh[j] && px < d->gw[j]) ? d->yhat[d->goff[j] + py * d->gw[j] + px] : 0.0f;
         }
       }
@@ -264,10 +275,10 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       Tile& C2 = tc[1][wave];
       Tile& C3 = tc[2][wave];
       // ---- context (FP32) in operand order: slot kk = 16 s + 8 hh + i
-      float r_in[CC_MAX_L - 1];
+      float r_in[CC_MAX_NIN];
 #pragma unroll
-      for (int q = 0; q < CC_MAX_L - 1; ++q)
-        r_in[q] = (has_ifce && q < nin) ? pwin[q][(x >> (q + 1)) - (x0 >> (q + 1))] : 0.0f;
+      for (int q = 0; q < CC_MAX_NIN; ++q)
+        r_in[q] = (has_ifce && q < nin) ? pwin[q][(x >> shq[q]) - (x0 >> shq[q])] : 0.0f;
       float cf[2][8];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
@@ -282,7 +293,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
             const int f = kk - S;
             float a = ib[f];
 #pragma unroll
-            for (int q = 0; q < CC_MAX_L - 1; ++q) a += iw[f][q] * r_in[q];
+            for (int q = 0; q < CC_MAX_NIN; ++q) a += iw[f][q] * r_in[q];
             v = a;
           }
           cf[s][i] = v;
@@ -345,8 +356,12 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       if (do_bwd && hh == 0) {
         C3.v[H2][n] = (__bf16)1.0f;
 #pragma unroll
-        for (int q = 0; q < CC_MAX_L - 1; ++q)
-          if (H2 + 1 + q < 32) C3.v[H2 + 1 + q][n] = (__bf16)r_in[q];
+        for (int q = 0; q < CC_MAX_NIN; ++q) {
+          if (q < Q3)
+            C3.v[H2 + 1 + q][n] = (__bf16)r_in[q];
+          else if (ifce_extra && H1 + 1 + q - Q3 < 32)
+            C2.v[H1 + 1 + q - Q3][n] = (__bf16)r_in[q];
+        }
       }
       const float p0 = __shfl_xor(o0, 32), p1 = __shfl_xor(o1, 32);
       const float mu = (o0 + p0) + (b30 + bs0);
@@ -419,6 +434,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
           const int m = mrow(i, hh);
           if (m >= S && m < CTX) {
             G3.v[2 + m - S][n] = (__bf16)(valid ? dc[i] : 0.0f);
+            if (ifce_extra && H2 + m - S < 32) G2.v[H2 + m - S][n] = (__bf16)(valid ? dc[i] : 0.0f);
             if (valid) d->df[d->dfoff[k][0] + (m - S) * nk + y * w + x] = dc[i];
           }
         }
@@ -546,6 +562,13 @@ int launch_t(const Launch& l, int bwd, hipStream_t st) {
 
 int cc_arm_fused_supported(const DevDesc& h) {
   if (h.S > NOFF) return 0;
+  // IFCE inputs beyond the last hidden tile's spare columns must fit in the
+  // second layer's spare rows and columns
+  const int Q3 = 32 - h.H2 - 1;
+  for (int k = 0; k < h.G; ++k) {
+    const int extra = h.nin[k] - Q3;
+    if (extra > 0 && (h.H2 + h.F > 32 || h.H1 + 1 + extra > 32)) return 0;
+  }
   for (int m = 0; m < h.S; ++m)
     if (h.dy[m] != CDY[m] || h.dx[m] != CDX[m]) return 0;
 #define X(a, b, c, e) if (h.S == a && h.F == b && h.H1 == c && h.H2 == e) return 1;

@@ -57,7 +57,7 @@ __device__ __forceinline__ float dsoftround(float x, float c, float invT) {
 
 __device__ __forceinline__ int grid_of(const CDesc* d, int i) {
   int k = 0;
-  while (k + 1 < d->L && i >= d->goff[k + 1]) ++k;
+  while (k + 1 < d->NG && i >= d->goff[k + 1]) ++k;
   return k;
 }
 
@@ -175,7 +175,8 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
 //   (d rate / d yhat + d distortion / d yhat) * d yhat / d y
 // where d rate / d yhat gathers, in a fixed order, the direct term, the
 // context gradients of the positions that use this latent as a causal
-// neighbour (reversed offsets) and the IFCE gradients of finer grids.
+// neighbour (reversed offsets) and the IFCE gradients of finer grids; a
+// hyperlatent (grid >= L) feeds every IFCE and has no distortion term.
 __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only_out, int adam) {
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
@@ -201,18 +202,21 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only
     }
   }
   const CF* P = (const CF*)(d->theta + d->n_lat);
-  const int nk = h * w;
-  for (int c = 0; c < d->G && c < k; ++c) {
-    const CF* W = P + d->p_iw[c];             // [F, L-c-1]
-    const int q = k - c - 1, nin = d->L - c - 1;
-    const float* D = d->df + d->dfoff[c][k - c];
+  const int nk = h * w, lev = d->glev[k];
+  const bool hyper = k >= d->L;
+  for (int c = 0; c < d->G && (hyper || c < k); ++c) {
+    const CF* W = P + d->p_iw[c];             // [F, nin[c]]
+    // input slot of this grid in the IFCE of grid c: the coarser latent
+    // grids first, then the hyperlatent grids
+    const int q = k - c - 1, nin = d->nin[c];
+    const float* D = d->df + d->dfoff[c][lev - c];   // pooled to this resolution
     for (int f = 0; f < d->F; ++f) g += W[f * nin + q] * D[f * nk + li];
   }
   if (rate_only_out) {
     rate_only_out[i] = g;
     return;
   }
-  g += d->dyq[i];
+  if (!hyper) g += d->dyq[i];
   g *= d->dq[i];
   d->grad[i] = g;
   if (adam && d->upd) adam_update(d, i, g);

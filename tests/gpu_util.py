@@ -11,8 +11,8 @@ def segments(mc, H, W):
     and per parameter tensor."""
     out = []
     pos = 0
-    for k in range(mc.L):
-        n = (H >> k) * (W >> k)
+    for k, lev in enumerate(wl.grid_levels(mc)):
+        n = (H >> lev) * (W >> lev)
         out.append((f"grid{k}", slice(pos, pos + n)))
         pos += n
     for name, shape, _ in wl.param_spec(mc):
@@ -77,7 +77,8 @@ def unexplained_outliers(mc, H, W, bad, sites):
     them, so they are held to the plain rule).  Returns the indices of `bad`
     that lie in no footprint."""
     L = mc.L
-    masks = [np.zeros((H >> k, W >> k), bool) for k in range(L)]
+    levels = wl.grid_levels(mc)
+    masks = [np.zeros((H >> lev, W >> lev), bool) for lev in levels]
     widths = {}
     for i, w in enumerate(mc.arm_hidden):
         widths[("arm", i)] = w
@@ -98,19 +99,20 @@ def unexplained_outliers(mc, H, W, bad, sites):
             continue
         k = tag[1]
         pos = idx // widths[("arm", tag[2])] if tag[0] == "arm" else idx
-        y, x = divmod(pos, W >> k)
+        y, x = divmod(pos, W >> levels[k])
         mark(k, y - 4, y, x - 4, x + 4)
         if k < mc.n_ifce_grids:
-            for j in range(k + 1, L):
-                mark(j, y >> (j - k), y >> (j - k), x >> (j - k), x >> (j - k))
-    starts = np.cumsum([0] + [(H >> k) * (W >> k) for k in range(L)])
+            for j in range(k + 1, len(levels)):
+                f = levels[j] - k
+                mark(j, y >> f, y >> f, x >> f, x >> f)
+    starts = np.cumsum([0] + [(H >> lev) * (W >> lev) for lev in levels])
     out = []
     for e in np.asarray(bad).tolist():
         k = int(np.searchsorted(starts, e, side="right") - 1)
-        if k >= L:
+        if k >= len(levels):
             out.append(e)
             continue
-        y, x = divmod(e - int(starts[k]), W >> k)
+        y, x = divmod(e - int(starts[k]), W >> levels[k])
         if not masks[k][y, x]:
             out.append(e)
     return out
@@ -151,7 +153,7 @@ def _oracle_grad(mc, H, W, theta, img, lam, quant, T, sigma, seed, t, tau, flip,
     import torch.nn.functional as Fnn
     cfg = mc.as_dict()
     th = torch.tensor(np.asarray(theta, np.float64), requires_grad=True)
-    n_lat = sum((H >> k) * (W >> k) for k in range(mc.L))
+    n_lat = wl.n_latents(mc, H, W)
     P = R.unpack_params(cfg, th[n_lat:])
     gy = R.split_latents(cfg, H, W, th[:n_lat])
     if quant == "soft":
@@ -180,7 +182,7 @@ def _oracle_grad(mc, H, W, theta, img, lam, quant, T, sigma, seed, t, tau, flip,
 
     bits = 0.0
     nl = len(mc.arm_hidden) + 1
-    for k in range(mc.L):
+    for k in range(len(grids)):
         c = R.arm_context(cfg, P, grids, k)
         x = c
         for i in range(nl):
@@ -274,8 +276,9 @@ def param_flip_slack(mc, H, W, theta, lam, sites, cap):
         c = s
         if F:
             if k < G:
-                r = torch.tensor([[float(grids[j][y >> (j - k), x >> (j - k)])
-                                   for j in range(k + 1, L)]], dtype=torch.float64)
+                lev = wl.grid_levels(mc)
+                r = torch.tensor([[float(grids[j][y >> (lev[j] - k), x >> (lev[j] - k)])
+                                   for j in range(k + 1, len(grids))]], dtype=torch.float64)
                 f = r @ P[f"ifce.{k}.w"].T + P[f"ifce.{k}.b"]
             else:
                 f = s.new_zeros(1, F)

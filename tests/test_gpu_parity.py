@@ -36,7 +36,10 @@ CASES = {
     "tiny_64x32_random": (wl.config_tiny, 64, 32, 13, True),
     "hop_512x768_init": (wl.config_hop, 512, 768, 2, False),
     "hop_320x1088_random": (wl.config_hop, 320, 1088, 14, True),   # ragged against every tile
-    # Table II presets
+    # hyperlatent grids (1/16 .. 1/64) feeding the IFCEs
+    "hop_hyper_128x192_random": (wl.config_hop_hyper, 128, 192, 19, True),
+    "hop_hyper_512x768_init": (wl.config_hop_hyper, 512, 768, 2, False),
+    # Table II presets (with their hyperlatent grids)
     "LOP_64x128_random": (lambda: wl.config_preset("LOP"), 64, 128, 15, True),
     "MOP_64x128_random": (lambda: wl.config_preset("MOP"), 64, 128, 16, True),
     "HOP_64x128_random": (lambda: wl.config_preset("HOP"), 64, 128, 17, True),
