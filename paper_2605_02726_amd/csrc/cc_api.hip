@@ -828,12 +828,10 @@ int ups_backward(cc_state* const* s, int n, hipStream_t st) {
   return CC_OK;
 }
 
-int forward_dist(cc_state* const* s, int n, int want_mse, hipStream_t st) {
+// Synthesis and residual layers of the distortion branch (+ MSE when
+// want_mse), after the upsampling.
+int forward_syn(cc_state* const* s, int n, int want_mse, hipStream_t st) {
   const DevDesc& h0 = s[0]->lo.h;
-  {
-    TimeScope ts(TK_UPS_FWD, st);
-    RET(ups_forward(s, n, st));
-  }
   const Launch lp = plan(s, n, [](const DevDesc& h) { return h.pix_ntile; });
   RET(cc_launch_syn_fwd_plain(lp, h0, (h0.n_res == 0 && want_mse) ? 1 : 0, st));
   for (int r = 0; r < h0.n_res; ++r) RET(cc_launch_res_fwd(lp, r, r == h0.n_res - 1, want_mse, st));
@@ -848,15 +846,29 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
   // longer than the whole distortion branch; sharing the units with it made
   // the step slower, so only the fused form forks
   Fork fk(h0.arm_fused ? s[0]->device : -1, st);
-  {
+  auto rate_branch = [&]() -> int {
     // rate branch (a2-a4, a10)
     const hipStream_t sr = fk.begin();
     RET(arm(s, n, backward ? 1 : 0, sr));
     if (backward && h0.G > 0) {
       RET(cc_launch_pool(plan(s, n, pool_blocks), sr));
     }
+    return CC_OK;
+  };
+#if CC_FORK_AT == 0
+  RET(rate_branch());
+#endif
+  {
+    TimeScope ts(TK_UPS_FWD, st);
+    RET(ups_forward(s, n, st));
   }
-  RET(forward_dist(s, n, 1, st));
+#if CC_FORK_AT == 1
+  RET(rate_branch());
+#endif
+  RET(forward_syn(s, n, 1, st));
+#if CC_FORK_AT == 2
+  RET(rate_branch());
+#endif
   if (backward) {
     const Launch lp = plan(s, n, [](const DevDesc& h) { return h.res_nwg; });
     int src_b = 0;
@@ -1186,7 +1198,8 @@ int cc_decode(cc_state* s, float* out_img_dev, void* stream) {
   p.temperature = 1.0f;
   hipStream_t st = (hipStream_t)stream;
   RET(quantise(&s, 1, &p, st));
-  RET(forward_dist(&s, 1, 0, st));
+  RET(ups_forward(&s, 1, st));
+  RET(forward_syn(&s, 1, 0, st));
   RET(cc_launch_copy_out(plan(&s, 1, [](const DevDesc& h) { return cdiv(3 * h.H * h.W, CC_ELT_TILE); }), out_img_dev, st));
   return CC_OK;
 }

@@ -145,9 +145,22 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
   {
     const int w0 = d->gw[c], n0 = d->gh[c] * w0;
     const float* src = d->df + d->dfoff[c][0] + (size_t)ch * n0;
-    for (int i = threadIdx.x; i < B * B; i += CC_ELT_TILE) {
-      const int y = i / B, x = i - y * B;
-      base[i] = src[(by * B + y) * w0 + bx * B + x];
+    // loads in groups of 8 per thread, each group issued before its LDS
+    // stores, so their latencies overlap
+    constexpr int NB = 8;
+    for (int i0 = 0; i0 < B * B; i0 += NB * CC_ELT_TILE) {
+      float v[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int i = i0 + u * CC_ELT_TILE + threadIdx.x;
+        const int y = i / B, x = i - y * B;
+        v[u] = i < B * B ? src[(by * B + y) * w0 + bx * B + x] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int i = i0 + u * CC_ELT_TILE + threadIdx.x;
+        if (i < B * B) base[i] = v[u];
+      }
     }
   }
   __syncthreads();

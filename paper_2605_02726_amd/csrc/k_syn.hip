@@ -134,14 +134,32 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
   {
     const float* gsrc = d->dU + d->uoff[j] + (size_t)ch * ho * wo;
     const float* tsrc = tchan(d, j, ch);
-    for (int i = tid; i < UG * UG; i += 256) {
+    // every load of the thread is issued before the first LDS store, so
+    // their latencies overlap
+    constexpr int NG = (UG * UG + 255) / 256, NT = (UTW * UTW + 255) / 256;
+    float gv[NG], tv[NT];
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+      const int i = tid + 256 * u;
       const int r = i / UG, c = i - r * UG;
       const int oy = 2 * iy0 - 3 + r, ox = 2 * ix0 - 3 + c;
-      g[r][c] = (oy >= 0 && oy < ho && ox >= 0 && ox < wo) ? gsrc[oy * wo + ox] : 0.0f;
+      gv[u] = (i < UG * UG && oy >= 0 && oy < ho && ox >= 0 && ox < wo) ? gsrc[oy * wo + ox] : 0.0f;
     }
-    for (int i = tid; i < UTW * UTW; i += 256) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int i = tid + 256 * u;
       const int r = i / UTW, c = i - r * UTW;
-      t[r][c] = tsrc[clampi(iy0 - 2 + r, 0, hi - 1) * wi + clampi(ix0 - 2 + c, 0, wi - 1)];
+      tv[u] = i < UTW * UTW ? tsrc[clampi(iy0 - 2 + r, 0, hi - 1) * wi + clampi(ix0 - 2 + c, 0, wi - 1)] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+      const int i = tid + 256 * u;
+      if (i < UG * UG) (&g[0][0])[(i / UG) * (UG + 1) + i % UG] = gv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int i = tid + 256 * u;
+      if (i < UTW * UTW) (&t[0][0])[(i / UTW) * (UTW + 1) + i % UTW] = tv[u];
     }
     __syncthreads();
     for (int i = tid; i < UG * UT; i += 256) {
@@ -989,16 +1007,35 @@ __global__ __launch_bounds__(256, 2) void k_res_bwd(Launch Lc, int r, int src_b)
   const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
   for (int tile = wgi; tile < ntx * nty; tile += nwg) {
     const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * TW;
-    __syncthreads();   // previous tile's reads are done (and wadj is written)
-    for (int i = tid; i < SH * SW; i += 256) {
+    // stage X_r (replicate-clamped halo) and the incoming gradient (zero
+    // halo): every load of the thread is issued before the first LDS store,
+    // so their latencies overlap
+    constexpr int NST = (SH * SW + 255) / 256;
+    float xv[NST][3], gv[NST][3];
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int i = tid + 256 * u;
       const int ly = i / SW, lx = i - ly * SW;
       const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
       const int cy = clampi(gy, 0, H - 1), cx = clampi(gx, 0, W - 1);
-      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      const bool in = i < SH * SW && gy >= 0 && gy < H && gx >= 0 && gx < W;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        xs[c][ly][lx] = X[(size_t)c * n + cy * W + cx];
-        gs[c][ly][lx] = in ? G[(size_t)c * n + gy * W + gx] : 0.0f;
+        xv[u][c] = i < SH * SW ? X[(size_t)c * n + cy * W + cx] : 0.0f;
+        gv[u][c] = in ? G[(size_t)c * n + gy * W + gx] : 0.0f;
+      }
+    }
+    __syncthreads();   // previous tile's reads are done (and wadj is written)
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int i = tid + 256 * u;
+      if (i < SH * SW) {
+        const int ly = i / SW, lx = i - ly * SW;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xs[c][ly][lx] = xv[u][c];
+          gs[c][ly][lx] = gv[u][c];
+        }
       }
     }
     __syncthreads();
