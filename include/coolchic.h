@@ -106,6 +106,12 @@ typedef struct cc_state cc_state;
  * H and W must be multiples of 2^(L-1). */
 int cc_config_supported(const cc_config* cfg, int H, int W);
 
+/* 1 if precision CC_BF16_FUSED runs this decoder shape's ARM on the matrix
+ * cores (the fused MFMA kernel covers the shape), 0 if that form falls back
+ * to the plain FP32 ARM kernel; -1 for an unsupported configuration.  The
+ * cfg's own precision field is ignored.  Host only. */
+int cc_arm_fused_available(const cc_config* cfg);
+
 /* Sizes. */
 int64_t cc_n_latents(const cc_config* cfg, int H, int W);
 int cc_n_params(const cc_config* cfg);

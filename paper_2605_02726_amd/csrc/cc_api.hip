@@ -959,6 +959,13 @@ int64_t cc_n_latents(const cc_config* cfg, int H, int W) {
   return n;
 }
 
+int cc_arm_fused_available(const cc_config* cfg) {
+  if (!cfg || check_config(cfg, 1 << (cfg->L - 1), 1 << (cfg->L - 1)) != CC_OK) return -1;
+  Layout lo;
+  build_layout(cfg, 1 << (cfg->L - 1), 1 << (cfg->L - 1), lo);
+  return cc_arm_fused_supported(lo.h) ? 1 : 0;
+}
+
 int cc_n_params(const cc_config* cfg) {
   if (check_config(cfg, 1 << (cfg ? cfg->L - 1 : 0), 1 << (cfg ? cfg->L - 1 : 0)) != CC_OK) return -1;
   Layout lo;

@@ -579,7 +579,8 @@ int launch_t(const Launch& l, int bwd, hipStream_t st) {
   X(6, 2, 5, 4)            \
   X(6, 2, 8, 8)            \
   X(10, 4, 10, 10)         \
-  X(14, 6, 20, 20)
+  X(14, 6, 20, 20)         \
+  X(20, 6, 26, 26)
 
 int cc_arm_fused_supported(const DevDesc& h) {
   if (h.S > NOFF) return 0;

@@ -91,3 +91,13 @@ def test_table2_presets_are_supported(lib, name):
     assert n == wl.n_params(mc)
     target = {"LOP": 500, "MOP": 1000, "HOP": 1900, "VHOP": 2700}[name]
     assert abs(n - target) <= 0.25 * target
+
+
+def test_fused_arm_covers_the_workload_and_the_presets(lib):
+    """The BF16 form runs the MFMA ARM kernel for the 512x768 workload's
+    decoder (with and without hyperlatents) and every Table II preset."""
+    L = lib.lib()
+    for mk in (wl.config_hop, wl.config_hop_hyper, wl.config_small,
+               *[lambda n=n: wl.config_preset(n) for n in ("LOP", "MOP", "HOP", "VHOP")]):
+        cfg = lib.make_config(mk(), lib.CC_BF16_FUSED)
+        assert L.cc_arm_fused_available(C.byref(cfg)) == 1
