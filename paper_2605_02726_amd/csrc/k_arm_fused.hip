@@ -245,13 +245,10 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   for (int seg = 0; seg < nseg; ++seg) {
     const int x0 = seg * SW;
     // stage latents: rows y0-4 .. y0+TH-1, columns x0-4 .. x0+SW+3 (zero
-    // outside), and the IFCE inputs of the band (every input grid is
-    // coarser, shift >= 1, and y0 is even, so both rows share each input
-    // row); every load of the thread is issued before the first LDS store,
-    // so their latencies overlap
+    // outside); every load of the thread is issued before the first LDS
+    // store, so their latencies overlap
     constexpr int NY = ((HALO + TH) * WR + NW * 64 - 1) / (NW * 64);
-    constexpr int NP = (CC_MAX_NIN * (SW / 2 + 1) + NW * 64 - 1) / (NW * 64);
-    float yv[NY], pv[NP];
+    float yv[NY];
 #pragma unroll
     for (int u = 0; u < NY; ++u) {
       const int i = tid + NW * 64 * u;
@@ -264,23 +261,16 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       const int i = tid + NW * 64 * u;
       if (i < (HALO + TH) * WR) (&ywin[0][0])[i] = yv[u];
     }
+    // IFCE inputs of the band: every input grid is coarser (shift >= 1)
+    // and y0 is even, so both rows share each input row
     if (has_ifce) {
-#pragma unroll
-      for (int u = 0; u < NP; ++u) {
-        const int i = tid + NW * 64 * u;
+      for (int i = tid; i < CC_MAX_NIN * (SW / 2 + 1); i += NW * 64) {
         const int q = i / (SW / 2 + 1), c = i - q * (SW / 2 + 1);
-        pv[u] = 0.0f;
         if (q < nin) {
           const int j = d->isrc[k][q], sh = d->ish[k][q];
           const int py = y0 >> sh, px = (x0 >> sh) + c;
-          if (py < d->gh[j] && px < d->gw[j]) pv[u] = d->yhat[d->goff[j] + py * d->gw[j] + px];
+          pwin[q][c] = (py < d->gh[j] && px < d->gw[j]) ? d->yhat[d->goff[j] + py * d->gw[j] + px] : 0.0f;
         }
-      }
-#pragma unroll
-      for (int u = 0; u < NP; ++u) {
-        const int i = tid + NW * 64 * u;
-        const int q = i / (SW / 2 + 1);
-        if (q < nin) (&pwin[0][0])[i] = pv[u];
       }
     }
     __syncthreads();
