@@ -846,29 +846,20 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
   // longer than the whole distortion branch; sharing the units with it made
   // the step slower, so only the fused form forks
   Fork fk(h0.arm_fused ? s[0]->device : -1, st);
-  auto rate_branch = [&]() -> int {
-    // rate branch (a2-a4, a10)
+  {
+    // rate branch (a2-a4, a10), forked before the distortion branch (later
+    // fork points measured slower: the ARM is the longer branch)
     const hipStream_t sr = fk.begin();
     RET(arm(s, n, backward ? 1 : 0, sr));
     if (backward && h0.G > 0) {
       RET(cc_launch_pool(plan(s, n, pool_blocks), sr));
     }
-    return CC_OK;
-  };
-#if CC_FORK_AT == 0
-  RET(rate_branch());
-#endif
+  }
   {
     TimeScope ts(TK_UPS_FWD, st);
     RET(ups_forward(s, n, st));
   }
-#if CC_FORK_AT == 1
-  RET(rate_branch());
-#endif
   RET(forward_syn(s, n, 1, st));
-#if CC_FORK_AT == 2
-  RET(rate_branch());
-#endif
   if (backward) {
     const Launch lp = plan(s, n, [](const DevDesc& h) { return h.res_nwg; });
     int src_b = 0;

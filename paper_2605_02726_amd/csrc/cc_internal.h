@@ -155,10 +155,6 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
 #define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
-#ifndef CC_FORK_AT
-#define CC_FORK_AT 0        // where the rate branch forks: 0 before the upsampling, 1 after it,
-                            // 2 after the synthesis forward
-#endif
 #ifndef CC_FUSED_MAXWG
 #define CC_FUSED_MAXWG 512  // fused ARM kernel: workgroups per image (each takes every n-th band)
 #endif

@@ -535,8 +535,9 @@ __device__ void stage_syn_weights(const CDesc* d, const CF* P, float* w) {
         v = P[d->p_sb[0] + a];
       else if (NH == 1)
         v = P[d->p_sw[1] + (e - 9) * W1 + a];
-    } else if (i < S::TAIL) {
-      const int r = i - S::N1, b = r / S::R2, e = r % S::R2;
+    } else if (NH == 2 && i < S::TAIL) {
+      constexpr int R2 = S::R2 > 0 ? S::R2 : 1;   // (no layer-2 records with one hidden layer)
+      const int r = i - S::N1, b = r / R2, e = r % R2;
       if (e < W1)
         v = P[d->p_sw[1] + b * W1 + e];
       else if (e == W1)
