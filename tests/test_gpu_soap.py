@@ -60,7 +60,7 @@ def _factors(mc, layout, flat):
     return out
 
 
-@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small])
+@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small, wl.config_hop_hyper])
 def test_first_call_sets_factors_and_eigenbases(mk):
     mc, H, W, img, lat, par, seed = _case(mk)
     lam, lr = 1e-3, 1e-2
@@ -100,9 +100,10 @@ def _oracle_after(mc, H, W, img, lat, par, seed, lam, n_steps, n_iter=200):
     return ora
 
 
+@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_hop_hyper])
 @pytest.mark.parametrize("n_before", [22, 19])    # next update: s = 23 (plain), s = 20 (refresh)
-def test_one_update_from_a_shared_state(n_before):
-    mc, H, W, img, lat, par, seed = _case()
+def test_one_update_from_a_shared_state(n_before, mk):
+    mc, H, W, img, lat, par, seed = _case(mk)
     lam = 1e-3
     ora = _oracle_after(mc, H, W, img, lat, par, seed, lam, n_before + 1)
     enc = _encoder(mc, img, lam, seed, lat, par)
