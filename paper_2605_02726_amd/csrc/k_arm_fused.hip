@@ -131,6 +131,11 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   // layer's tile, paired with the context-gradient rows H2 + f there (the
   // host checks that they fit)
   constexpr int Q3 = 32 - H2 - 1;
+  // The linear stabilizer rides in the first layer's spare output rows H1,
+  // H1 + 1 (and its backward in the same columns of the transposed layer):
+  // register IS of half HS holds row H1, register IS + 1 row H1 + 1.
+  static_assert((H1 & 3) != 3, "stabilizer rows must share a register group");
+  constexpr int IS = (H1 / 8) * 4 + (H1 & 3), HS = (H1 & 7) / 4;
   __shared__ float ywin[HALO + TH][WR];
   // context-gradient accumulators: one private window per wavefront (its 32
   // columns plus HALO on each side, the band rows plus HALO above), merged
@@ -190,13 +195,17 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
         const int kk = 16 * s2 + 8 * hh + i, u = kunit(kk), m = n;
         float v = 0.0f;
         if (mat == 0)
-          v = (m < H1 && kk < CTX) ? w1s[m * CTX + kk] : 0.0f;
+          v = kk >= CTX ? 0.0f
+              : m < H1 ? w1s[m * CTX + kk]
+              : m < H1 + 2 ? vec[4 + m - H1][kk] : 0.0f;   // stabilizer rows
         else if (mat == 1)
           v = (m < H2 && u < H1) ? w2s[m * H1 + u] : 0.0f;
         else if (mat == 2)
           v = (m < H1 && u < H2) ? w2s[u * H1 + m] : 0.0f;
         else
-          v = (m < CTX && u < H1) ? w1s[u * CTX + m] : 0.0f;
+          v = m >= CTX ? 0.0f
+              : u < H1 ? w1s[u * CTX + m]
+              : u < H1 + 2 ? vec[4 + u - H1][m] : 0.0f;    // stabilizer columns
         hi[i] = (__bf16)v;
         lo[i] = (__bf16)(v - (float)hi[i]);
       }
@@ -321,22 +330,11 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
           for (int i = 0; i < 8; ++i) C1.v[16 * s + 8 * hh + i][n] = bc[s][i];
         if (hh == 0) C1.v[CTX][n] = (__bf16)1.0f;
       }
-      // stabilizer (FP32) while the context is live
-      float o0 = 0.0f, o1 = 0.0f;
-      if (stab) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int kk = 16 * s + 8 * hh + i;
-            o0 += vec[4][kk] * cf[s][i];
-            o1 += vec[5][kk] * cf[s][i];
-          }
-      }
-      // ---- layer 1 and 2
+      // ---- layer 1 (with the stabilizer in rows H1, H1 + 1) and 2
       f32x16 z = {};
       f32x16 D = mfma3(wop[0][0][lane], wopl[0][0][lane], bc[0], bcl[0], z);
       if (CTX > 16) D = mfma3(wop[0][1][lane], wopl[0][1][lane], bc[1], bcl[1], D);
+      float o0 = hh == HS ? D[IS] : 0.0f, o1 = hh == HS ? D[IS + 1] : 0.0f;
       unsigned m1 = 0, m2 = 0;
       bf16x8 bh[2], bhl[2];
       {
@@ -416,23 +414,23 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
         float gv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) gv[i] = ((m1 >> i) & 1u) ? D[i] : 0.0f;
+        // (d mu, d l) enter at the stabilizer rows: the transposed first layer
+        // then adds the stabilizer's context gradient, and the weight-gradient
+        // tile gets its rows H1, H1 + 1
+        gv[IS] = hh == HS ? dmu : 0.0f;
+        gv[IS + 1] = hh == HS ? dl : 0.0f;
         split8(gv, bd[0], bdl[0]);
         split8(gv + 8, bd[1], bdl[1]);
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) G1.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
-      if (hh == 0) {
-        G1.v[H1][n] = (__bf16)dmu;
-        G1.v[H1 + 1][n] = (__bf16)dl;
-      }
       D = mfma3(wop[3][0][lane], wopl[3][0][lane], bd[0], bdl[0], z);
       D = mfma3(wop[3][1][lane], wopl[3][1][lane], bd[1], bdl[1], D);
       float dc[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int m = mrow(i, hh);
-        dc[i] = D[i] + (vec[4][m] * dmu + vec[5][m] * dl);
-        G3.v[m][n] = (__bf16)0.0f;
+        dc[i] = D[i];
+        G3.v[mrow(i, hh)][n] = (__bf16)0.0f;
       }
       __builtin_amdgcn_wave_barrier();
       if (hh == 0) {
