@@ -251,20 +251,24 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   if (tid < (HALO + TH) * 2 * HALO) (&cin[0][0])[tid] = 0.0f;
 
   const int nseg = (w + SW - 1) / SW;
-  for (int seg = 0; seg < nseg; ++seg) {
-    const int x0 = seg * SW;
-    // stage latents: rows y0-4 .. y0+TH-1, columns x0-4 .. x0+SW+3 (zero
-    // outside); every load of the thread is issued before the first LDS
-    // store, so their latencies overlap
-    constexpr int NY = ((HALO + TH) * WR + NW * 64 - 1) / (NW * 64);
-    float yv[NY];
+  // latent window of a segment: rows y0-4 .. y0+TH-1, columns x0-4 ..
+  // x0+SW+3 (zero outside), loaded into registers (every load issued before
+  // any use, so their latencies overlap); the next segment's window is
+  // loaded while the current one's context gradients are merged
+  constexpr int NY = ((HALO + TH) * WR + NW * 64 - 1) / (NW * 64);
+  float yv[NY];
+  auto load_window = [&](int xs) {
 #pragma unroll
     for (int u = 0; u < NY; ++u) {
       const int i = tid + NW * 64 * u;
       const int r = i / WR, c = i - r * WR;
-      const int gy = y0 - HALO + r, gx = x0 - HALO + c;
+      const int gy = y0 - HALO + r, gx = xs - HALO + c;
       yv[u] = (i < (HALO + TH) * WR && gy >= 0 && gy < h && gx >= 0 && gx < w) ? yg[gy * w + gx] : 0.0f;
     }
+  };
+  load_window(0);
+  for (int seg = 0; seg < nseg; ++seg) {
+    const int x0 = seg * SW;
 #pragma unroll
     for (int u = 0; u < NY; ++u) {
       const int i = tid + NW * 64 * u;
@@ -475,6 +479,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       }
     }
     __syncthreads();
+    if (seg + 1 < nseg) load_window(x0 + SW);   // in flight during the merge
     // ---- merge the wavefront windows (fixed order) with the carried
     // columns, write the finished columns of this segment and carry the last
     // 2*HALO columns into the next one.  Row rr of the window is grid row
