@@ -38,7 +38,7 @@ PEAKS = {
 # calibration (FETCH x2.000, WRITE x1.000); the commands and the table are in
 # profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
 # until the counters are taken again.
-ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3581.2 + 1.0 * 18678.1) * 1024)
+ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3585.1 + 1.0 * 18675.9) * 1024)
 
 
 def arm_flops_per_step(mc, H, W):
