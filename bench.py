@@ -58,7 +58,7 @@ def arm_flops_per_step(mc, H, W):
 
 
 def measure_step(precision, steps, warmup, timing=True, optimizer="adam", nn_quantize=False,
-                 overlap=True, hyper=False):
+                 overlap=True, hyper=False, shape=None):
     import ctypes as C
     import numpy as np
     import torch
@@ -67,12 +67,12 @@ def measure_step(precision, steps, warmup, timing=True, optimizer="adam", nn_qua
 
     prev = set_branch_overlap(overlap)
     try:
-        return _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper)
+        return _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper, shape)
     finally:
         set_branch_overlap(prev)
 
 
-def _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper):
+def _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper, shape):
     import ctypes as C
     import numpy as np
     import torch
@@ -85,6 +85,8 @@ def _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hype
     lat = np.zeros(wl.n_latents(mc, H, W), np.float32)
     enc = Encoder(mc, img, lam, seed, lat, wl.init_params(mc, seed), precision=precision,
                   optimizer=optimizer)
+    if shape:
+        enc.set_launch_shape(**shape)
     L = _lib.lib()
     t = 0
     for _ in range(warmup):
@@ -145,19 +147,19 @@ def hbm_bytes_per_step(mc, H, W):
     }
 
 
-def measure_kernel(precision, kernel, steps=20, warmup=3):
+def measure_kernel(precision, kernel, steps=20, warmup=3, shape=None):
     """Average duration (ms) per step of one kernel class, live with HIP
     events on the launch stream, with the two branches of the step in order
     (the kernel alone on the chip, not sharing it with the other branch)."""
     from paper_2605_02726_amd.encoder import set_branch_overlap
     prev = set_branch_overlap(False)
     try:
-        return _measure_kernel(precision, kernel, steps, warmup)
+        return _measure_kernel(precision, kernel, steps, warmup, shape)
     finally:
         set_branch_overlap(prev)
 
 
-def _measure_kernel(precision, kernel, steps, warmup):
+def _measure_kernel(precision, kernel, steps, warmup, shape):
     import ctypes as C
     import numpy as np
     import torch
@@ -168,6 +170,8 @@ def _measure_kernel(precision, kernel, steps, warmup):
     enc = Encoder(mc, torch.from_numpy(wl.image_large(2)), 1e-3, 2,
                   np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, 2),
                   precision=precision)
+    if shape:
+        enc.set_launch_shape(**shape)
     L = _lib.lib()
     for t in range(1, warmup + 1):
         enc.step(t, *schedule(t, 1000), sync=False)
@@ -256,6 +260,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=16, help="serving trace length (0 = skip)")
     ap.add_argument("--serve-iters", type=int, default=2000)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library's default launch shapes (no autotuning before timing)")
+    ap.add_argument("--launch-shape", default=None, metavar="ARM_WGS,SYN_CPW,RES_TPW",
+                    help="fixed launch shape of the plain-decoder forms instead of tuning")
     ap.add_argument("--no-soap", action="store_true", help="skip the SOAP form of the step")
     ap.add_argument("--only-step", action="store_true",
                     help="time only the single-image step (for profiler runs)")
@@ -279,23 +287,47 @@ def main():
     from paper_2605_02726_amd import workloads as wl
     assert torch.cuda.is_available(), "bench.py needs the GPU"
 
+    # launch shapes: tuned on the same workload before any timed region
+    # (coordinate descent over the tunable kernels' workgroup shapes)
+    shapes, tuning = {}, {}
+    if args.launch_shape:
+        a, c, r = (int(x) for x in args.launch_shape.split(","))
+        fixed = {"arm_wgs": a, "syn_chunks_per_wg": c, "res_tiles_per_wg": r}
+        shapes = {p: fixed for p in ("fp32", "bf16")}
+        tuning = {"fixed": fixed}
+    elif not args.no_tune:
+        from paper_2605_02726_amd import autotune
+        plist = ["fp32", "bf16"] if args.precision == "both" else [args.precision]
+        cases = [(p, False) for p in plist] + ([] if args.no_soap else [(plist[-1], True)])
+        for p, hyp in cases:
+            mc_t = wl.config_hop_hyper() if hyp else wl.config_hop()
+            r = autotune.tune(mc_t, 512, 768, p, steps=30)
+            key = p + ("_hyper" if hyp else "")
+            shapes[key] = r["shape"]
+            tuning[key] = {"shape": r["shape"], "trials": len(r["trials"]),
+                           "tuned_ms": round(r["ms_per_step"], 4),
+                           "default_ms": round(r["default_ms_per_step"], 4)}
+
     forms = {}
     for p in (["fp32", "bf16"] if args.precision == "both" else [args.precision]):
         forms[p] = measure_step(p, args.steps, args.warmup, not args.no_kernel_timing,
-                                nn_quantize=(p == "bf16" and not args.only_step))
+                                nn_quantize=(p == "bf16" and not args.only_step), shape=shapes.get(p))
+        if p in shapes:
+            forms[p]["launch_shape"] = shapes[p]
     head = "bf16" if "bf16" in forms else "fp32"
     main_f = forms[head]
     # the same step with the rate and distortion branches in order on one
     # stream (no concurrency): the ARM kernel's duration alone
-    serial = measure_step(head, args.steps, args.warmup, not args.no_kernel_timing, overlap=False)
+    serial = measure_step(head, args.steps, args.warmup, not args.no_kernel_timing, overlap=False,
+                          shape=shapes.get(head))
     if not args.no_soap:
         # the same step with SOAP on the decoder parameters (Section IV-B)
-        f = measure_step(head, args.steps, args.warmup, False, optimizer="soap")
+        f = measure_step(head, args.steps, args.warmup, False, optimizer="soap", shape=shapes.get(head))
         f["optimizer"] = "soap (decoder parameters), adam (latents)"
         f["overhead_vs_adam"] = round(f["ms_per_step"] / main_f["ms_per_step"] - 1.0, 4)
         forms[head + "_soap"] = f
         # the same step with three hyperlatent grids (Section III-A.3)
-        f = measure_step(head, args.steps, args.warmup, False, hyper=True)
+        f = measure_step(head, args.steps, args.warmup, False, hyper=True, shape=shapes.get(head + "_hyper"))
         f["decoder"] = "2277 parameters: the same with 1/16, 1/32, 1/64 hyperlatent grids"
         f["overhead_vs_plain"] = round(f["ms_per_step"] / main_f["ms_per_step"] - 1.0, 4)
         forms[head + "_hyper"] = f
@@ -331,7 +363,7 @@ def main():
         bts = hbm_bytes_per_step(mc, H, W)
         hbm = {}
         for name in ("ups_fwd", "ups_bwd", "join"):
-            ms = measure_kernel(head, name)
+            ms = measure_kernel(head, name, shape=shapes.get(head))
             hbm[name] = {"ms_per_step": round(ms, 4), "bytes_per_step": bts[name], "branches": "in order",
                          "achieved_GBs": round(bts[name] / (ms / 1e3) / 1e9, 1),
                          "peak_GBs": PEAKS["hbm_GBs"],
@@ -380,6 +412,7 @@ def main():
         "batched_16_images": batched,
         "serving": serving,
         "cpu_baseline": cpu,
+        "autotune": tuning or None,
     }
     out["serial_branches"] = {"value": round(serial["value"], 3),
                               "ms_per_step": round(serial["ms_per_step"], 4),

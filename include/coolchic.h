@@ -264,6 +264,23 @@ int cc_syn_fwd(cc_state* s, const float* zhat, const float* params, float* xhat,
 int cc_syn_bwd(cc_state* s, const float* grad_xhat, float* grad_zhat, float* grad_params,
                void* stream);
 
+/* Launch shape of the tunable kernels of a state (for an autotuner; the
+ * results differ only by the order of the weight-gradient partial sums):
+ *   arm_wgs            fused ARM workgroups per image, 1 .. the number of
+ *                      2-row bands of all grids (each workgroup takes every
+ *                      arm_wgs-th band);
+ *   syn_chunks_per_wg  64-pixel chunks per synthesis-backward workgroup,
+ *                      4 .. 64;
+ *   res_tiles_per_wg   8 x 64 tiles per residual-adjoint workgroup, 1 .. 16.
+ * 0 keeps a value.  cc_set_launch_shape synchronises `stream` (the state's
+ * last step must be finished before its descriptor changes); CC_EINVAL for
+ * a value out of range.  cc_get_launch_shape also returns the number of
+ * bands (the largest arm_wgs); any pointer may be NULL.  Host side only. */
+int cc_set_launch_shape(cc_state* s, int arm_wgs, int syn_chunks_per_wg, int res_tiles_per_wg,
+                        void* stream);
+int cc_get_launch_shape(const cc_state* s, int* arm_wgs, int* syn_chunks_per_wg,
+                        int* res_tiles_per_wg, int* arm_bands);
+
 /* Live kernel timing for measurement tools: HIP events are recorded on the
  * launch stream around every launch of one kernel class ("arm", "syn_bwd",
  * "res_bwd", "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which

@@ -92,6 +92,9 @@ _PROTOS = [
     ("cc_syn_bwd", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cc_timing_enable", C.c_int, [C.c_char_p]),
     ("cc_set_branch_overlap", C.c_int, [C.c_int]),
+    ("cc_set_launch_shape", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    ("cc_get_launch_shape", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("cc_arm_fused_available", C.c_int, [C.c_void_p]),
     ("cc_timing_read", C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     ("cc_free_state", None, [C.c_void_p]),

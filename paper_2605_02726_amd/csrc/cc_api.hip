@@ -98,6 +98,9 @@ int ups_chain_first(const DevDesc& h) {
   return jc;
 }
 
+// Tiles of the residual-layer adjoint.
+int res_tiles(const DevDesc& h) { return cdiv(h.H, CC_RES_TH) * cdiv(h.W, CC_RES_TW); }
+
 // Workgroups of the tiled upsampling adjoint at level j: one per (channel of
 // T_j, 16x16 tile of grid j); none for the chain levels.
 int ups_tile_wgs(const DevDesc& h, int j) {
@@ -255,7 +258,8 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.arm_nwg = std::max(h.arm_nwg_plain, h.arm_nwg_fused);
   const int npix = H * W;
   h.syn_nchunk = cdiv(npix, CC_SYN_CHUNK);
-  h.syn_nwg = cdiv(h.syn_nchunk, CC_SYN_CPW);
+  h.syn_cpw = CC_SYN_CPW;
+  h.syn_nwg = cdiv(h.syn_nchunk, h.syn_cpw);
   h.pix_ntile = cdiv(npix, CC_PIX_TILE);
   h.pix_nwg = h.pix_ntile;
   h.lat_ntile = cdiv(h.n_lat, CC_ELT_TILE);
@@ -272,17 +276,21 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
     wpo += (long long)rows * 4;
   }
   h.prod_syn = q;
+  // partial rows sized for the smallest tunable chunks per workgroup
   h.prod[q++] = {h.p_sw[0], syn_end - h.p_sw[0], h.syn_nwg, 0, wpo};
-  wpo += (long long)h.syn_nwg * (syn_end - h.p_sw[0]);
+  wpo += (long long)cdiv(h.syn_nchunk, CC_SYN_CPW_MIN) * (syn_end - h.p_sw[0]);
   h.prod_res0 = q;
-  h.res_nwg = cdiv(cdiv(H, CC_RES_TH) * cdiv(W, CC_RES_TW), CC_RES_TPW);
+  h.res_tpw = CC_RES_TPW;
+  h.res_nwg = cdiv(res_tiles(h), h.res_tpw);
   for (int r = 0; r < h.n_res; ++r) {
+    // partial rows sized for one tile per workgroup
     h.prod[q++] = {h.p_rw[r], 84, h.res_nwg, 0, wpo};
-    wpo += (long long)h.res_nwg * 84;
+    wpo += (long long)res_tiles(h) * 84;
   }
   h.nprod = q;
   h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
   h.prod[h.prod_arm].nrows = h.arm_nwg;
+  h.arm_wgs = std::min(h.arm_nwg_fused, CC_FUSED_MAXWG);
 
   // weight-gradient tables: (index into gradient vector, index into
   // activation vector, grid requirement) per parameter, matching the LDS row
@@ -793,7 +801,7 @@ int arm(cc_state* const* s, int n, int bwd, hipStream_t st) {
   // per compute unit for one image, leaving room on each unit for the
   // distortion branch running beside it); the plain kernel has one per chunk
   const Launch l = plan(s, n, [](const DevDesc& h) {
-    return h.arm_fused ? std::min(h.arm_nwg, CC_FUSED_MAXWG) : h.arm_nwg;
+    return h.arm_fused ? h.arm_wgs : h.arm_nwg;
   });
   TimeScope ts(bwd ? TK_ARM : TK_NONE, st);
   if (s[0]->lo.h.arm_fused) return cc_launch_arm_fused(l, s[0]->lo.h, bwd, st);
@@ -1404,6 +1412,46 @@ int cc_set_precision(cc_state* s, int precision) {
   h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
   h.prod[h.prod_arm].nrows = h.arm_nwg;
   HIPCHK(hipMemcpy(s->ddev, &h, sizeof(DevDesc), hipMemcpyHostToDevice));
+  return CC_OK;
+}
+
+int cc_set_launch_shape(cc_state* s, int arm_wgs, int syn_chunks_per_wg, int res_tiles_per_wg,
+                        void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  DevDesc& h = s->lo.h;
+  if (arm_wgs < 0 || arm_wgs > h.arm_nwg_fused)
+    return fail(CC_EINVAL, "arm_wgs=%d outside [1, %d] (0 keeps it)", arm_wgs, h.arm_nwg_fused);
+  if (syn_chunks_per_wg != 0 && (syn_chunks_per_wg < CC_SYN_CPW_MIN || syn_chunks_per_wg > CC_SYN_CPW_MAX))
+    return fail(CC_EINVAL, "synthesis chunks per workgroup %d outside [%d, %d]", syn_chunks_per_wg,
+                CC_SYN_CPW_MIN, CC_SYN_CPW_MAX);
+  if (res_tiles_per_wg < 0 || res_tiles_per_wg > CC_RES_TPW_MAX)
+    return fail(CC_EINVAL, "residual tiles per workgroup %d outside [1, %d]", res_tiles_per_wg, CC_RES_TPW_MAX);
+  // no step of this state may still read the descriptor (the side stream's
+  // work joins back into the caller's stream, so this waits for it too)
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  if (arm_wgs > 0) h.arm_wgs = arm_wgs;
+  if (syn_chunks_per_wg > 0) {
+    h.syn_cpw = syn_chunks_per_wg;
+    h.syn_nwg = cdiv(h.syn_nchunk, h.syn_cpw);
+    h.prod[h.prod_syn].nrows = h.syn_nwg;
+  }
+  if (res_tiles_per_wg > 0) {
+    h.res_tpw = res_tiles_per_wg;
+    h.res_nwg = cdiv(res_tiles(h), h.res_tpw);
+    for (int r = 0; r < h.n_res; ++r) h.prod[h.prod_res0 + r].nrows = h.res_nwg;
+  }
+  HIPCHK(hipMemcpy(s->ddev, &h, sizeof(DevDesc), hipMemcpyHostToDevice));
+  return CC_OK;
+}
+
+int cc_get_launch_shape(const cc_state* s, int* arm_wgs, int* syn_chunks_per_wg, int* res_tiles_per_wg,
+                        int* arm_bands) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  const DevDesc& h = s->lo.h;
+  if (arm_wgs) *arm_wgs = h.arm_wgs;
+  if (syn_chunks_per_wg) *syn_chunks_per_wg = h.syn_cpw;
+  if (res_tiles_per_wg) *res_tiles_per_wg = h.res_tpw;
+  if (arm_bands) *arm_bands = h.arm_nwg_fused;
   return CC_OK;
 }
 

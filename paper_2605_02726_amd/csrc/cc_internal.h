@@ -54,6 +54,8 @@ struct DevDesc {
   int arm_nchunk, arm_nwg, syn_nchunk, syn_nwg, pix_nwg, nprod;
   int lat_ntile, pix_ntile, res_nwg;
   int ups_jc;                   // first upsampling level run by the per-source chain kernels (L: none)
+  int arm_wgs;                  // fused ARM: workgroups per image (each takes every arm_wgs-th band)
+  int syn_cpw, res_tpw;         // synthesis chunks / residual tiles per workgroup (launch shape)
   ProdSeg prod[CC_MAX_PROD];
   int prod_arm, prod_syn, prod_res0, prod_ups1;   // producer indices
   // ---- buffers (device pointers inside the slab)
@@ -150,8 +152,11 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_ARM_CPW 4        // ARM kernel: chunks per workgroup
 #define CC_SYN_CHUNK 64
 #ifndef CC_SYN_CPW
-#define CC_SYN_CPW 12
+#define CC_SYN_CPW 12       // synthesis backward: default chunks per workgroup
 #endif
+#define CC_SYN_CPW_MIN 4    // smallest tunable (the partial-row space is sized for it)
+#define CC_SYN_CPW_MAX 64
+#define CC_RES_TPW_MAX 16   // residual adjoint: largest tunable tiles per workgroup
 #define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
 #define CC_FUSED_BAND 2     // fused ARM kernel: rows per band

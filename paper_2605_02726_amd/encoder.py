@@ -139,6 +139,18 @@ class Encoder:
         check(lib().cc_rd_eval(self.handle, C.byref(r), _stream()))
         return dict(bits=r.bits, bpp=r.bpp, mse=r.mse, psnr=r.psnr, loss=r.loss)
 
+    def set_launch_shape(self, arm_wgs: int = 0, syn_chunks_per_wg: int = 0,
+                         res_tiles_per_wg: int = 0):
+        """Launch shape of the tunable kernels (0 keeps a value)."""
+        check(lib().cc_set_launch_shape(self.handle, int(arm_wgs), int(syn_chunks_per_wg),
+                                        int(res_tiles_per_wg), _stream()))
+
+    def launch_shape(self) -> dict:
+        v = [C.c_int(0) for _ in range(4)]
+        check(lib().cc_get_launch_shape(self.handle, *[C.byref(x) for x in v]))
+        return dict(arm_wgs=v[0].value, syn_chunks_per_wg=v[1].value,
+                    res_tiles_per_wg=v[2].value, arm_bands=v[3].value)
+
     def nn_quantize(self):
         """Choose the quantisation steps and Exp-Golomb orders of the decoder
         parameters by rate-distortion cost and leave the state with the

@@ -41,8 +41,10 @@ class Job:
 class Server:
     def __init__(self, mc, precision: str = "bf16", hbm_budget: int = 64 << 30,
                  max_slots: int = _lib.CC_MAX_BATCH, check_every: int = 50,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, shapes=None):
         self.mc = mc
+        # autotune.ShapeCache (or None): tuned launch shapes applied at admission
+        self.shapes = shapes
         self.precision = precision
         self.budget = int(hbm_budget)
         self.max_slots = min(int(max_slots), _lib.CC_MAX_BATCH)
@@ -83,9 +85,13 @@ class Server:
                 still.append(job)
                 continue
             _, H, W = job.image.shape
-            lat = np.zeros(sum((H >> k) * (W >> k) for k in range(self.mc.L)), np.float32)
-            enc = Encoder(self.mc, torch.from_numpy(job.image), job.lam, job.seed, lat,
+            # latents start at zero (latents=None); the decoder from job.params
+            enc = Encoder(self.mc, torch.from_numpy(job.image), job.lam, job.seed, None,
                           job.params, precision=self.precision)
+            if self.shapes is not None:
+                shape = self.shapes.get(self.mc, self.precision, H, W)
+                if shape is not None:
+                    enc.set_launch_shape(**shape)
             self.used += enc.nbytes
             self.peak_used = max(self.peak_used, self.used)
             job.admitted = self.now()
