@@ -17,6 +17,10 @@ Parity status by function (see the tests under tests/test_oracle_*.py):
   laplace_bin_prob, latent_bits  pinned (sum to one, closed forms)
   upsample                       pinned (bicubic interpolation routine,
                                  constants, explicit loops)
+  upsampling Conv refinement     pinned (scipy 1-D convolution with
+  (conv_taps, conv1d)            replicated edges, identity taps equal the
+                                 plain upsampling, constants, central finite
+                                 differences)
   synthesis                      pinned (scipy correlation, explicit loops)
   forward, loss_and_grad         pinned (closed-form totals, central finite
                                  differences)

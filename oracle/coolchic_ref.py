@@ -29,6 +29,12 @@ independently there):
   * upsampling level j: symmetric 8-tap kernel (h0 h1 h2 h3 h3 h2 h1 h0) used
     as a stride-2 transposed convolution on rows then columns, replicate edge;
     T_{L-1} = yhat^(L-1), T_{j-1} = concat(yhat^(j-1), Up_j(T_j));
+  * upsampling Conv refinement (optional, ups_conv = 1): before its
+    transposed convolution, level j filters T_j with a symmetric separable
+    7-tap kernel (c3 c2 c1 c0 c1 c2 c3) on rows then columns (stride 1,
+    replicate edge, every channel), i.e. Up_j(T) = TConv_j(Conv_j(T)); its
+    four taps follow the transposed convolutions' in the parameter vector,
+    level by level, and start at (1, 0, 0, 0), the identity;
   * synthesis: ReLU after each hidden 1x1 layer, stabilizer added to the trunk
     output, then x <- x + Conv3x3(x) per residual layer (replicate padding,
     no activation);
@@ -102,6 +108,9 @@ def unpack_params(cfg: Dict, flat) -> Dict[str, torch.Tensor]:
                    (f"ifce.{k}.b", (cfg["n_ifce_feat"],))]
     for j in range(1, L):
         shapes.append((f"ups.{j}", (4,)))
+    if cfg.get("ups_conv", 0):
+        for j in range(1, L):
+            shapes.append((f"ups.{j}.conv", (4,)))
     widths = [L] + list(cfg["syn_hidden"]) + [3]
     for i in range(len(widths) - 1):
         shapes += [(f"syn.{i}.w", (widths[i + 1], widths[i])), (f"syn.{i}.b", (widths[i + 1],))]
@@ -129,7 +138,7 @@ def n_params(cfg: Dict) -> int:
     n += (2 * ctx + 2) if cfg["arm_stab"] else 0
     n += sum(cfg["n_ifce_feat"] * ifce_inputs(cfg, k) + cfg["n_ifce_feat"]
              for k in range(cfg["n_ifce_grids"]))
-    n += 4 * (L - 1)
+    n += 4 * (L - 1) * (2 if cfg.get("ups_conv", 0) else 1)   # TConv (and Conv) taps
     widths = [L] + list(cfg["syn_hidden"]) + [3]
     n += sum(widths[i] * widths[i + 1] + widths[i + 1] for i in range(len(widths) - 1))
     n += (3 * L + 3) if cfg["syn_stab"] else 0
@@ -285,11 +294,32 @@ def up1d(x, u, dim: int):
     return out
 
 
+def conv_taps(c):
+    """7-tap symmetric kernel (c3 c2 c1 c0 c1 c2 c3) from its 4 free taps."""
+    return torch.stack([c[3], c[2], c[1], c[0], c[1], c[2], c[3]])
+
+
+def conv1d(x, k, dim: int):
+    """Stride-1 convolution with the 7-tap symmetric kernel k along one axis,
+    replicate edge: out[o] = sum over a in -3..3 of k[a+3] x[clamp(o+a, 0, n-1)]."""
+    n = x.shape[dim]
+    o = torch.arange(n)
+    out = 0.0
+    for a in range(-3, 4):
+        out = out + k[a + 3] * torch.index_select(x, dim, torch.clamp(o + a, 0, n - 1))
+    return out
+
+
 def upsample(cfg, P, grids):
-    """zhat = f_upsilon(yhat), shape (L, H, W) (Section III-B)."""
+    """zhat = f_upsilon(yhat), shape (L, H, W) (Section III-B); with the Conv
+    refinement each level filters its input before the transposed
+    convolution."""
     L = cfg["L"]
     T = grids[L - 1][None]
     for j in range(L - 1, 0, -1):
+        if cfg.get("ups_conv", 0):
+            k = conv_taps(P[f"ups.{j}.conv"])
+            T = conv1d(conv1d(T, k, 1), k, 2)
         u = up_taps(P[f"ups.{j}"])
         T = up1d(up1d(T, u, 1), u, 2)
         T = torch.cat([grids[j - 1][None], T], dim=0)

@@ -18,7 +18,9 @@ The flat parameter vector follows one documented order (shared interface, see
            then, with the ARM stabilizer, Ws [2, in], bs [2]
   IFCE     for grid k = 0 .. n_ifce_grids-1: W [F, L-k-1 + n_hyper], b [F]
   upsample for level j = 1 .. L-1: the 4 free taps (h0, h1, h2, h3) of the
-           symmetric 8-tap kernel (h0 h1 h2 h3 h3 h2 h1 h0)
+           symmetric 8-tap kernel (h0 h1 h2 h3 h3 h2 h1 h0); then, with the
+           Conv refinement, for level j = 1 .. L-1 the 4 free taps
+           (c0, c1, c2, c3) of the symmetric 7-tap kernel (c3 c2 c1 c0 c1 c2 c3)
   synthesis for each 1x1 layer: W [out, in], b [out];
            then, with the synthesis stabilizer, Ws [3, L], bs [3];
            then for each residual 3x3 layer: W [3, 3, 3, 3] (out, in, ky, kx), b [3]
@@ -35,6 +37,9 @@ import numpy as np
 # the bicubic interpolation taps for a factor-2 upsampling, used to initialise
 # every learned upsampling level.  All four values are exact dyadic fractions.
 BICUBIC_TAPS = (-0.03515625, -0.10546875, 0.26171875, 0.87890625)
+# Free taps (c0, c1, c2, c3) of the optional 7-tap upsampling Conv at start:
+# the identity filter.
+IDENTITY_CONV_TAPS = (1.0, 0.0, 0.0, 0.0)
 
 
 @dataclass
@@ -54,6 +59,7 @@ class ModelConfig:
     p_min: float = 2.0 ** -16
     n_hyper: int = 0                # hyperlatent grids, resolutions 1/2^b .. 1/2^(b+n_hyper-1)
     hyper_first: int = 4            # b
+    ups_conv: int = 0               # 1: each upsampling level filters its input (7-tap Conv) first
 
     def as_dict(self):
         return asdict(self)
@@ -103,6 +109,24 @@ def config_hop_hyper() -> ModelConfig:
     return c
 
 
+def config_hop_conv() -> ModelConfig:
+    """The 512x768 workload's decoder with the upsampling Conv refinement
+    (6 levels x 4 more taps: 2,247 decoder parameters)."""
+    c = config_hop()
+    c.ups_conv = 1
+    return c
+
+
+def conv_taps_offsets(cfg: ModelConfig):
+    """Offsets of every level's Conv taps in the decoder-parameter vector."""
+    out, pos = [], 0
+    for name, shape, _ in param_spec(cfg):
+        if name.endswith(".conv"):
+            out.append(pos)
+        pos += int(np.prod(shape))
+    return out
+
+
 def config_tiny() -> ModelConfig:
     """A small shape with every feature switched on, for brute-force tests."""
     return ModelConfig(L=4, n_spatial=6, n_ifce_feat=2, n_ifce_grids=2,
@@ -127,6 +151,9 @@ def param_spec(cfg: ModelConfig):
         spec.append((f"ifce.{k}.b", (cfg.n_ifce_feat,), nin))
     for j in range(1, cfg.L):
         spec.append((f"ups.{j}", (4,), 0))
+    if cfg.ups_conv:
+        for j in range(1, cfg.L):
+            spec.append((f"ups.{j}.conv", (4,), 0))
     widths = [cfg.L] + list(cfg.syn_hidden) + [3]
     for i in range(len(widths) - 1):
         spec.append((f"syn.{i}.w", (widths[i + 1], widths[i]), widths[i]))
@@ -169,7 +196,8 @@ def init_params(cfg: ModelConfig, seed: int, arm_out_zero: bool = True,
     for name, shape, fan_in in param_spec(cfg):
         n = int(np.prod(shape))
         if name.startswith("ups."):
-            out.append(np.array(BICUBIC_TAPS, dtype=np.float64))
+            taps = IDENTITY_CONV_TAPS if name.endswith(".conv") else BICUBIC_TAPS
+            out.append(np.array(taps, dtype=np.float64))
             continue
         bound = scale / math.sqrt(fan_in)
         vals = rng.uniform(-bound, bound, size=n)
