@@ -58,7 +58,7 @@ def arm_flops_per_step(mc, H, W):
 
 
 def measure_step(precision, steps, warmup, timing=True, optimizer="adam", nn_quantize=False,
-                 overlap=True, hyper=False, shape=None):
+                 overlap=True, hyper=False, shape=None, conv=False):
     import ctypes as C
     import numpy as np
     import torch
@@ -67,19 +67,20 @@ def measure_step(precision, steps, warmup, timing=True, optimizer="adam", nn_qua
 
     prev = set_branch_overlap(overlap)
     try:
-        return _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper, shape)
+        return _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper, shape,
+                             conv)
     finally:
         set_branch_overlap(prev)
 
 
-def _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper, shape):
+def _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hyper, shape, conv):
     import ctypes as C
     import numpy as np
     import torch
     from paper_2605_02726_amd import _lib, workloads as wl
     from paper_2605_02726_amd.encoder import Encoder, schedule
 
-    mc = wl.config_hop_hyper() if hyper else wl.config_hop()
+    mc = wl.config_hop_hyper() if hyper else (wl.config_hop_conv() if conv else wl.config_hop())
     H, W, seed, lam, n_iter = 512, 768, 2, 1e-3, 1000
     img = torch.from_numpy(wl.image_large(seed))
     lat = np.zeros(wl.n_latents(mc, H, W), np.float32)
@@ -331,6 +332,11 @@ def main():
         f["decoder"] = "2277 parameters: the same with 1/16, 1/32, 1/64 hyperlatent grids"
         f["overhead_vs_plain"] = round(f["ms_per_step"] / main_f["ms_per_step"] - 1.0, 4)
         forms[head + "_hyper"] = f
+        # the same step with the upsampling Conv refinement (Section III-B)
+        f = measure_step(head, args.steps, args.warmup, False, conv=True, shape=shapes.get(head))
+        f["decoder"] = "2247 parameters: the same with a 7-tap Conv before each upsampling level"
+        f["overhead_vs_plain"] = round(f["ms_per_step"] / main_f["ms_per_step"] - 1.0, 4)
+        forms[head + "_conv"] = f
 
     mc = wl.config_hop()
     H, W = 512, 768

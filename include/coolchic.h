@@ -84,6 +84,14 @@ typedef struct cc_config {
    * b + n_hyper <= L (each resolution is one of the latent grids'). */
   int n_hyper;
   int hyper_first;
+  /* Upsampling Conv refinement (Section III-B: the upsampling combines
+   * symmetric separable convolutions and transposed convolutions): 1 =
+   * before its transposed convolution, level j filters T_j with the
+   * symmetric 7-tap kernel (c3 c2 c1 c0 c1 c2 c3) on rows then columns
+   * (stride 1, replicate edge, every channel); its 4 free taps per level
+   * follow the transposed convolutions' taps in the parameter vector and
+   * start at (1, 0, 0, 0), the identity.  0 = none. */
+  int ups_conv;
 } cc_config;
 
 /* Per-iteration scalars (Table I schedules are evaluated by the caller). */

@@ -34,7 +34,8 @@ class cc_config(C.Structure):
                 ("n_syn_hidden", C.c_int), ("syn_hidden", C.c_int * 2), ("syn_stab", C.c_int),
                 ("n_res", C.c_int), ("logscale_min", C.c_float), ("logscale_max", C.c_float),
                 ("p_min", C.c_float), ("precision", C.c_int), ("n_hyper", C.c_int),
-                ("hyper_first", C.c_int)]
+                ("hyper_first", C.c_int),
+                ("ups_conv", C.c_int)]
 
 
 class cc_step_params(C.Structure):
@@ -145,6 +146,7 @@ def make_config(mc, precision: int = CC_FP32_PLAIN) -> cc_config:
     c.logscale_max = mc.logscale_max
     c.n_hyper = int(getattr(mc, "n_hyper", 0))
     c.hyper_first = int(getattr(mc, "hyper_first", 4))
+    c.ups_conv = int(getattr(mc, "ups_conv", 0))
     c.p_min = mc.p_min
     c.precision = precision
     return c

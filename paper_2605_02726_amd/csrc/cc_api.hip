@@ -68,7 +68,7 @@ struct Layout {
   DevDesc h{};          // host copy (pointers filled relative to a base)
   size_t bytes = 0;
   size_t off_desc = 0, off_img, off_theta, off_m, off_v, off_grad, off_yhat, off_dq, off_dyd,
-         off_dyq, off_dc, off_df, off_U, off_dU, off_X, off_dXa, off_dXb, off_wp, off_wp2,
+         off_dyq, off_dc, off_df, off_U, off_dU, off_V, off_dV, off_X, off_dXa, off_dXb, off_wp, off_wp2,
          off_agt, off_sgt, off_lpb, off_lpm, off_scal, off_aft;
   std::vector<unsigned> arm_gtab, syn_gtab, arm_ftab;
   std::vector<int> soap_tab;
@@ -111,6 +111,12 @@ int ups_tile_wgs(const DevDesc& h, int j) {
 // per source grid on the chain levels.
 int ups_bwd_rows(const DevDesc& h, int j) { return j < h.ups_jc ? ups_tile_wgs(h, j) : h.L - j; }
 
+// Workgroups of the Conv refinement's adjoint at level j: one per (channel
+// of T_j, CC_UPC_TILE positions of grid j); none without the refinement.
+int upc_wgs(const DevDesc& h, int j) {
+  return h.ups_conv ? cdiv(h.gh[j] * h.gw[j], CC_UPC_TILE) * (h.L - j) : 0;
+}
+
 int check_config(const cc_config* c, int H, int W) {
   if (!c) return fail(CC_EINVAL, "config is NULL");
   if (c->L < 2 || c->L > CC_MAX_L) return fail(CC_EINVAL, "L=%d outside [2, %d]", c->L, CC_MAX_L);
@@ -137,6 +143,7 @@ int check_config(const cc_config* c, int H, int W) {
     return fail(CC_EINVAL, "hyperlatent grids from 1/2^%d (%d of them) need n_ifce_grids <= first and first + n <= L",
                 c->hyper_first, c->n_hyper);
   if (c->L + c->n_hyper > CC_MAX_G) return fail(CC_EINVAL, "too many grids");
+  if (c->ups_conv != 0 && c->ups_conv != 1) return fail(CC_EINVAL, "ups_conv=%d is not 0 or 1", c->ups_conv);
   if (c->n_ifce_grids > 0 && c->L - 1 + c->n_hyper > CC_MAX_NIN)
     return fail(CC_EINVAL, "an IFCE would have more than %d inputs", CC_MAX_NIN);
   if (!(c->logscale_min < c->logscale_max)) return fail(CC_EINVAL, "log-scale clamp");
@@ -219,6 +226,11 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
     h.p_ups[j] = p;
     p += 4;
   }
+  h.ups_conv = c->ups_conv;
+  for (int j = 1; j < h.L; ++j) {
+    h.p_upc[j] = h.ups_conv ? p : -1;
+    if (h.ups_conv) p += 4;
+  }
   const int nsl = h.n_syn_hidden + 1;
   for (int i = 0; i < nsl; ++i) {
     h.p_sw[i] = p;
@@ -268,11 +280,18 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.prod_arm = q;
   h.prod[q++] = {0, h.n_arm_par, h.arm_nwg, 0, wpo};
   wpo += (long long)std::max(h.arm_nwg_plain, h.arm_nwg_fused) * h.n_arm_par;
-  h.ups_jc = ups_chain_first(h);
+  // the chain kernels have no Conv refinement: with it every level is tiled
+  h.ups_jc = h.ups_conv ? h.L : ups_chain_first(h);
   h.prod_ups1 = q;
   for (int j = 1; j < h.L; ++j) {
     const int rows = ups_bwd_rows(h, j);
     h.prod[q++] = {h.p_ups[j], 4, rows, 0, wpo};
+    wpo += (long long)rows * 4;
+  }
+  h.prod_upc1 = q;
+  for (int j = 1; h.ups_conv && j < h.L; ++j) {
+    const int rows = upc_wgs(h, j);
+    h.prod[q++] = {h.p_upc[j], 4, rows, 0, wpo};
     wpo += (long long)rows * 4;
   }
   h.prod_syn = q;
@@ -410,6 +429,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
       ts.push_back({h.p_ib[k], 1, {h.F, 1, 1, 1}});
     }
     for (int j = 1; j < h.L; ++j) ts.push_back({h.p_ups[j], 1, {4, 1, 1, 1}});
+    for (int j = 1; h.ups_conv && j < h.L; ++j) ts.push_back({h.p_upc[j], 1, {4, 1, 1, 1}});
     for (int i = 0; i <= h.n_syn_hidden; ++i) {
       ts.push_back({h.p_sw[i], 2, {h.syn_w[i + 1], h.syn_w[i], 1, 1}});
       ts.push_back({h.p_sb[i], 1, {h.syn_w[i + 1], 1, 1, 1}});
@@ -468,6 +488,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
       mark(h.p_ib[k], h.F, 7);
     }
     for (int j = 1; j < h.L; ++j) mark(h.p_ups[j], 4, 4);
+    for (int j = 1; h.ups_conv && j < h.L; ++j) mark(h.p_upc[j], 4, 4);
     for (int i = 0; i <= h.n_syn_hidden; ++i) {
       mark(h.p_sw[i], h.syn_w[i + 1] * h.syn_w[i], 2);
       mark(h.p_sb[i], h.syn_w[i + 1], 3);
@@ -514,6 +535,13 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   }
   Lo.off_U = take(sizeof(float) * un);
   Lo.off_dU = take(sizeof(float) * un);
+  size_t vn = 0;
+  for (int j = 1; j < h.L; ++j) {
+    h.voff[j] = (int)vn;
+    if (h.ups_conv) vn += (size_t)(h.L - j) * h.gh[j] * h.gw[j];
+  }
+  Lo.off_V = take(sizeof(float) * std::max<size_t>(vn, 1));
+  Lo.off_dV = take(sizeof(float) * std::max<size_t>(vn, 1));
   Lo.off_X = take(sizeof(float) * (size_t)(h.n_res + 1) * 3 * npix);
   Lo.off_dXa = take(sizeof(float) * 3 * (size_t)npix);
   Lo.off_dXb = take(sizeof(float) * 3 * (size_t)npix);
@@ -551,6 +579,8 @@ void set_pointers(Layout& Lo, char* base) {
   h.df = (float*)(base + Lo.off_df);
   h.U = (float*)(base + Lo.off_U);
   h.dU = (float*)(base + Lo.off_dU);
+  h.V = (float*)(base + Lo.off_V);
+  h.dV = (float*)(base + Lo.off_dV);
   h.X = (float*)(base + Lo.off_X);
   h.dXa = (float*)(base + Lo.off_dXa);
   h.dXb = (float*)(base + Lo.off_dXb);
@@ -597,6 +627,7 @@ void default_params(const DevDesc& h, uint64_t seed, std::vector<float>& P) {
   const float bic[4] = {-0.03515625f, -0.10546875f, 0.26171875f, 0.87890625f};
   for (int j = 1; j < h.L; ++j)
     for (int t = 0; t < 4; ++t) P[h.p_ups[j] + t] = bic[t];
+  for (int j = 1; h.ups_conv && j < h.L; ++j) P[h.p_upc[j]] = 1.0f;   // identity Conv
   for (int i = 0; i <= h.n_syn_hidden; ++i)
     fill(h.p_sw[i], h.syn_w[i + 1] * h.syn_w[i] + h.syn_w[i + 1], h.syn_w[i]);
   if (h.syn_stab) fill(h.p_ssw, 3 * h.L + 3, h.L);
@@ -638,7 +669,7 @@ Launch plan(cc_state* const* s, int n, F count) {
 
 bool same_shape(const cc_state* a, const cc_state* b) {
   const DevDesc &x = a->lo.h, &y = b->lo.h;
-  return x.L == y.L && x.NG == y.NG && x.hyper_first == y.hyper_first && x.S == y.S && x.F == y.F && x.G == y.G && x.H1 == y.H1 && x.H2 == y.H2 &&
+  return x.L == y.L && x.NG == y.NG && x.hyper_first == y.hyper_first && x.ups_conv == y.ups_conv && x.S == y.S && x.F == y.F && x.G == y.G && x.H1 == y.H1 && x.H2 == y.H2 &&
          x.n_syn_hidden == y.n_syn_hidden && x.syn_w[1] == y.syn_w[1] &&
          x.syn_w[2] == y.syn_w[2] && x.n_res == y.n_res && a->precision == b->precision;
 }
@@ -816,6 +847,11 @@ int ups_forward(cc_state* const* s, int n, hipStream_t st) {
   const Launch lc = plan(s, n, [](const DevDesc& h) { return h.L - h.ups_jc; });
   if (lc.tile0[n] > 0) RET(cc_launch_ups_fwd_chain(lc, st));
   for (int j = s[0]->lo.h.L - 1; j >= 1; --j) {
+    // Conv refinement: V_j = Conv_j(T_j), the transposed convolution's input
+    const Launch lv = plan(s, n, [j](const DevDesc& h) {
+      return h.ups_conv ? cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE) : 0;
+    });
+    if (lv.tile0[n] > 0) RET(cc_launch_upc_fwd(lv, j, st));
     const Launch l = plan(s, n, [j](const DevDesc& h) {
       return j < h.ups_jc ? cdiv(h.gh[j - 1] * h.gw[j - 1], CC_PIX_TILE) : 0;
     });
@@ -830,6 +866,8 @@ int ups_backward(cc_state* const* s, int n, hipStream_t st) {
   for (int j = 1; j < s[0]->lo.h.L; ++j) {
     const Launch l = plan(s, n, [j](const DevDesc& h) { return ups_tile_wgs(h, j); });
     if (l.tile0[n] > 0) RET(cc_launch_ups_bwd(l, j, st));
+    const Launch lv = plan(s, n, [j](const DevDesc& h) { return upc_wgs(h, j); });
+    if (lv.tile0[n] > 0) RET(cc_launch_upc_bwd(lv, j, st));
   }
   const Launch lc = plan(s, n, [](const DevDesc& h) { return h.L - h.ups_jc; });
   if (lc.tile0[n] > 0) RET(cc_launch_ups_bwd_chain(lc, st));
@@ -1338,7 +1376,8 @@ int cc_ups_bwd(cc_state* s, const float* grad_zhat, float* grad_yhat, float* gra
   RET(copy_d2d(h.dU + h.uoff[1], grad_zhat + npx, sizeof(float) * (h.L - 1) * npx, st));
   RET(ups_backward(one, 1, st));
   if (grad_yhat) RET(copy_d2d(grad_yhat, h.dyq, sizeof(float) * h.n_lat, st));
-  if (grad_params) RET(params_grad_out(s, grad_params, h.p_ups[1], h.p_ups[1] + 4 * (h.L - 1), st));
+  if (grad_params)
+    RET(params_grad_out(s, grad_params, h.p_ups[1], h.p_ups[1] + 4 * (h.L - 1) * (h.ups_conv ? 2 : 1), st));
   return CC_OK;
 }
 

@@ -11,7 +11,7 @@
 #define CC_MAX_G 12   // grids of the flat latent pyramid (latent + hyperlatent)
 #define CC_MAX_NIN 10 // inputs of one IFCE (coarser latent grids + hyperlatent grids)
 #define CC_MAX_S 32
-#define CC_MAX_PROD 16
+#define CC_MAX_PROD 24
 
 // One producer of weight-gradient partial rows (a kernel whose workgroups
 // each write the sum of their positions' contributions to a parameter range).
@@ -36,10 +36,12 @@ struct DevDesc {
   // IFCE of grid k < G: its inputs (pyramid grid, resolution shift)
   int nin[4], isrc[4][CC_MAX_NIN], ish[4][CC_MAX_NIN];
   int uoff[CC_MAX_L];           // U_j (j >= 1): (L-j) channels at grid j-1
+  int ups_conv;                 // 1: level j filters T_j (7-tap Conv) before its transposed convolution
+  int voff[CC_MAX_L];           // V_j = Conv_j(T_j) (j >= 1): (L-j) channels at grid j
   int dfoff[4][CC_MAX_L];       // IFCE df pyramid of child grid c at level f
   int dy[CC_MAX_S], dx[CC_MAX_S];
   // ---- parameter offsets (within the decoder parameters)
-  int p_aw[3], p_ab[3], p_asw, p_asb, p_iw[4], p_ib[4], p_ups[CC_MAX_L];
+  int p_aw[3], p_ab[3], p_asw, p_asb, p_iw[4], p_ib[4], p_ups[CC_MAX_L], p_upc[CC_MAX_L];
   int p_sw[3], p_sb[3], p_ssw, p_ssb, p_rw[4], p_rb[4];
   int n_arm_par;                // ARM + IFCE parameters: [0, n_arm_par)
   // ---- scalars
@@ -57,10 +59,10 @@ struct DevDesc {
   int arm_wgs;                  // fused ARM: workgroups per image (each takes every arm_wgs-th band)
   int syn_cpw, res_tpw;         // synthesis chunks / residual tiles per workgroup (launch shape)
   ProdSeg prod[CC_MAX_PROD];
-  int prod_arm, prod_syn, prod_res0, prod_ups1;   // producer indices
+  int prod_arm, prod_syn, prod_res0, prod_ups1, prod_upc1;   // producer indices
   // ---- buffers (device pointers inside the slab)
   float *img, *theta, *m, *v, *grad, *yhat, *dq, *dc, *df, *dyd, *dyq;
-  float *U, *dU, *X, *dXa, *dXb, *wp;
+  float *U, *dU, *V, *dV, *X, *dXa, *dXb, *wp;
   double* wp2;
   unsigned* arm_gtab;
   unsigned* arm_ftab;           // fused ARM: parameter -> (grid, accumulator, row, column)
@@ -135,6 +137,8 @@ int cc_launch_poke(float* p, float v, hipStream_t st);
 int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_ups_fwd_chain(const Launch& l, hipStream_t st);
+int cc_launch_upc_fwd(const Launch& l, int j, hipStream_t st);
+int cc_launch_upc_bwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_ups_bwd_chain(const Launch& l, hipStream_t st);
 int cc_launch_syn_fwd(const Launch& l, const DevDesc& h, int final_mse, int precision, hipStream_t st);
 int cc_launch_syn_bwd(const Launch& l, const DevDesc& h, int precision, hipStream_t st);
@@ -164,6 +168,7 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_FUSED_MAXWG 512  // fused ARM kernel: workgroups per image (each takes every n-th band)
 #endif
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
+#define CC_UPC_TILE 256     // upsampling Conv adjoint: positions per workgroup
 #define CC_UPS_COARSE 2048  // upsampling levels whose output grid has at most this many positions
                             // run as one workgroup per source grid, all such levels in LDS
 #define CC_UPS_CHAIN_T 1024 // threads of those workgroups

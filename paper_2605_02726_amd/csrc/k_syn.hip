@@ -8,7 +8,10 @@
 // Up_j is the symmetric 8-tap kernel (h0 h1 h2 h3 h3 h2 h1 h0) applied as a
 // stride-2 transposed convolution (padding 3, replicate edge) on rows and on
 // columns: output o reads the 4 inputs clamp((o + 3 - t) / 2) for the taps t
-// with the parity of o + 3.  zhat = [yhat^(0); U_1].
+// with the parity of o + 3.  zhat = [yhat^(0); U_1].  With the Conv
+// refinement, level j first filters T_j with the symmetric 7-tap kernel
+// (c3 c2 c1 c0 c1 c2 c3) on rows and columns (replicate edge), V_j =
+// Conv_j(T_j), and the transposed convolution reads V_j instead of T_j.
 #include "cc_internal.h"
 
 #include <math.h>
@@ -32,6 +35,12 @@ __device__ __forceinline__ float tapv(const float* h, int t) { return h[t < 4 ? 
 // Input channel ch of T_j at position p (grid j).
 __device__ __forceinline__ const float* tchan(const CDesc* d, int j, int ch) {
   return ch == 0 ? d->yhat + d->goff[j] : d->U + d->uoff[j + 1] + (size_t)(ch - 1) * d->gh[j] * d->gw[j];
+}
+
+// Input channel ch of the transposed convolution of level j: V_j with the
+// Conv refinement, else T_j.
+__device__ __forceinline__ const float* usrc(const CDesc* d, int j, int ch) {
+  return d->ups_conv ? d->V + d->voff[j] + (size_t)ch * d->gh[j] * d->gw[j] : tchan(d, j, ch);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -65,7 +74,7 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_ups_fwd(Launch L, int j) {
   const int nch = d->L - j;
   float* out = d->U + d->uoff[j];
   for (int ch = 0; ch < nch; ++ch) {
-    const float* in = tchan(d, j, ch);
+    const float* in = usrc(d, j, ch);
     float s = 0.0f;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -133,7 +142,7 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
   float dh[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   {
     const float* gsrc = d->dU + d->uoff[j] + (size_t)ch * ho * wo;
-    const float* tsrc = tchan(d, j, ch);
+    const float* tsrc = usrc(d, j, ch);
     // every load of the thread is issued before the first LDS store, so
     // their latencies overlap
     constexpr int NG = (UG * UG + 255) / 256, NT = (UTW * UTW + 255) / 256;
@@ -184,7 +193,9 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
         float a = 0.0f;
 #pragma unroll
         for (int b = 0; b < 8; ++b) a += wys[q][b] * R[2 * q + b][p];
-        if (ch == 0)
+        if (d->ups_conv)
+          d->dV[d->voff[j] + (size_t)ch * hi * wi + iy * wi + ix] = a;
+        else if (ch == 0)
           d->dyq[d->goff[j] + iy * wi + ix] = a;
         else
           d->dU[d->uoff[j + 1] + (size_t)(ch - 1) * hi * wi + iy * wi + ix] = a;
@@ -231,6 +242,149 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
     const float s2 = (sh[tid][0] + sh[tid][1]) + (sh[tid][2] + sh[tid][3]);
     const long long pg_off = d->prod[d->prod_ups1 + j - 1].off;
     d->wp[pg_off + (size_t)wgi * 4 + tid] = s2;
+  }
+}
+
+// ------------------------------------------------- Conv refinement ----
+// 7-tap symmetric kernel k[0..6] = (c3 c2 c1 c0 c1 c2 c3) of level j.
+__device__ __forceinline__ void conv_kernel7(const CDesc* d, int j, float* k) {
+  const CF* c = (const CF*)(d->theta + d->n_lat + d->p_upc[j]);
+  k[3] = c[0];
+  k[2] = k[4] = c[1];
+  k[1] = k[5] = c[2];
+  k[0] = k[6] = c[3];
+}
+
+// V_j = Conv_j(T_j): one thread per position of grid j, all channels;
+// V[y][x] = sum_a k[a] sum_b k[b] T[clamp(y + a - 3)][clamp(x + b - 3)].
+__global__ __launch_bounds__(CC_PIX_TILE) void k_upc_fwd(Launch L, int j) {
+  const int im = cc_find_img(L, blockIdx.x);
+  const CDesc* d = (const CDesc*)L.d[im];
+  const int hi = d->gh[j], wi = d->gw[j], n = hi * wi;
+  const int p = (blockIdx.x - L.tile0[im]) * CC_PIX_TILE + threadIdx.x;
+  if (p >= n) return;
+  const int y = p / wi, x = p - y * wi;
+  float k[7];
+  conv_kernel7(d, j, k);
+  int ry[7], cx[7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    ry[a] = clampi(y + a - 3, 0, hi - 1) * wi;
+    cx[a] = clampi(x + a - 3, 0, wi - 1);
+  }
+  const int nch = d->L - j;
+  float* out = d->V + d->voff[j];
+  for (int ch = 0; ch < nch; ++ch) {
+    const float* in = tchan(d, j, ch);
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      float r = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 7; ++b) r += k[b] * in[ry[a] + cx[b]];
+      s += k[a] * r;
+    }
+    out[(size_t)ch * n + p] = s;
+  }
+}
+
+// Weights of the outputs o = i - 3 .. i + 3 on input i along one axis of
+// length n (the clamped 7-tap filter's adjoint); 0 for outputs outside.
+__device__ __forceinline__ void conv_adj_w(const float* k, int i, int n, float* w) {
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    const int o = i + a - 3;
+    float s = 0.0f;
+    if (o >= 0 && o < n) {
+#pragma unroll
+      for (int e = 0; e < 7; ++e)
+        if (clampi(o + e - 3, 0, n - 1) == i) s += k[e];
+    }
+    w[a] = s;
+  }
+}
+
+// Adjoint of Conv_j: one workgroup per (channel of T_j, CC_UPC_TILE
+// positions of grid j).  dT_j = Conv_j^T(dV_j) goes to the distortion
+// gradient of yhat^(j) (channel 0) or to dU_{j+1}; the tap gradients are
+// sum over outputs o of dV[o] * dV[o]/dc_q, with dV[o]/dc_q the row sums
+// (over b, weighted by k[b]) of the rows a with |a - 3| = q plus the column
+// sums of the columns b with |b - 3| = q.  One partial row of 4 tap gradients
+// per workgroup.
+__global__ __launch_bounds__(CC_UPC_TILE) void k_upc_bwd(Launch L, int j) {
+  __shared__ float sh[4][CC_UPC_TILE / 64];
+  const int im = cc_find_img(L, blockIdx.x);
+  const CDesc* d = (const CDesc*)L.d[im];
+  const int wgi = blockIdx.x - L.tile0[im];
+  const int hi = d->gh[j], wi = d->gw[j], n = hi * wi;
+  const int nt = (n + CC_UPC_TILE - 1) / CC_UPC_TILE;
+  const int ch = wgi / nt;
+  const int tid = threadIdx.x;
+  const int p = (wgi - ch * nt) * CC_UPC_TILE + tid;
+  float k[7];
+  conv_kernel7(d, j, k);
+  float dc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (p < n) {
+    const int y = p / wi, x = p - y * wi;
+    const float* T = tchan(d, j, ch);
+    const float* G = d->dV + d->voff[j] + (size_t)ch * n;
+    float awy[7], awx[7];
+    conv_adj_w(k, y, hi, awy);
+    conv_adj_w(k, x, wi, awx);
+    float g = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      const int oy = y + a - 3;
+      if (oy < 0 || oy >= hi) continue;
+      float r = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 7; ++b) {
+        const int ox = x + b - 3;
+        if (ox >= 0 && ox < wi) r += awx[b] * G[oy * wi + ox];
+      }
+      g += awy[a] * r;
+    }
+    if (ch == 0)
+      d->dyq[d->goff[j] + p] = g;
+    else
+      d->dU[d->uoff[j + 1] + (size_t)(ch - 1) * n + p] = g;
+    int ry[7], cx[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      ry[a] = clampi(y + a - 3, 0, hi - 1) * wi;
+      cx[a] = clampi(x + a - 3, 0, wi - 1);
+    }
+    float rows[7], cols[7];
+#pragma unroll
+    for (int b = 0; b < 7; ++b) cols[b] = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      float r = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 7; ++b) {
+        const float t = T[ry[a] + cx[b]];
+        r += k[b] * t;
+        cols[b] += k[a] * t;
+      }
+      rows[a] = r;
+    }
+    const float gv = G[p];
+    dc[0] = gv * (rows[3] + cols[3]);
+#pragma unroll
+    for (int q = 1; q < 4; ++q) dc[q] = gv * ((rows[3 - q] + rows[3 + q]) + (cols[3 - q] + cols[3 + q]));
+  }
+  const int wv = tid >> 6, ln = tid & 63;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float s2 = wave_sum(dc[q]);
+    if (ln == 0) sh[q][wv] = s2;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    float s2 = 0.0f;
+#pragma unroll
+    for (int w = 0; w < CC_UPC_TILE / 64; ++w) s2 += sh[tid][w];
+    d->wp[d->prod[d->prod_upc1 + j - 1].off + (size_t)wgi * 4 + tid] = s2;
   }
 }
 
@@ -1171,6 +1325,14 @@ int cc_launch_syn_bwd_plain(const Launch& l, const DevDesc& h, int src_b, hipStr
 
 int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st) {
   hipLaunchKernelGGL(k_ups_fwd, dim3(l.tile0[l.n]), dim3(CC_PIX_TILE), 0, st, l, j);
+  return ok();
+}
+int cc_launch_upc_fwd(const Launch& l, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_upc_fwd, dim3(l.tile0[l.n]), dim3(CC_PIX_TILE), 0, st, l, j);
+  return ok();
+}
+int cc_launch_upc_bwd(const Launch& l, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_upc_bwd, dim3(l.tile0[l.n]), dim3(CC_UPC_TILE), 0, st, l, j);
   return ok();
 }
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st) {

@@ -182,13 +182,14 @@ def n_latents(cfg: ModelConfig, H: int, W: int) -> int:
 
 
 def init_params(cfg: ModelConfig, seed: int, arm_out_zero: bool = True,
-                scale: float = 1.0) -> np.ndarray:
+                scale: float = 1.0, conv_jitter: float = 0.0) -> np.ndarray:
     """Seeded initial decoder parameters (float32).
 
     Weights and biases ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) * scale; the last
     ARM layer (and the ARM stabilizer) are zero when ``arm_out_zero`` so that
     every latent starts with mu = 0 and log-scale = 0; upsampling taps start
-    at the bicubic kernel.
+    at the bicubic kernel, the upsampling Conv taps (if any) at the identity
+    plus ``conv_jitter`` times standard normal draws.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
@@ -196,8 +197,12 @@ def init_params(cfg: ModelConfig, seed: int, arm_out_zero: bool = True,
     for name, shape, fan_in in param_spec(cfg):
         n = int(np.prod(shape))
         if name.startswith("ups."):
-            taps = IDENTITY_CONV_TAPS if name.endswith(".conv") else BICUBIC_TAPS
-            out.append(np.array(taps, dtype=np.float64))
+            if name.endswith(".conv"):
+                taps = np.array(IDENTITY_CONV_TAPS) + (conv_jitter * rng.standard_normal(4)
+                                                       if conv_jitter else 0.0)
+            else:
+                taps = np.array(BICUBIC_TAPS)
+            out.append(taps.astype(np.float64))
             continue
         bound = scale / math.sqrt(fan_in)
         vals = rng.uniform(-bound, bound, size=n)

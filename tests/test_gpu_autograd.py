@@ -20,7 +20,7 @@ def _case(mk=wl.config_hop, H=64, W=128, seed=41):
     rng = np.random.default_rng(seed)
     yhat = np.round(rng.normal(scale=2.0, size=wl.n_latents(mc, H, W))).astype(np.float32)
     yhat += rng.uniform(-0.4, 0.4, size=yhat.shape).astype(np.float32)   # training-like values
-    par = wl.init_params(mc, seed, arm_out_zero=False)
+    par = wl.init_params(mc, seed, arm_out_zero=False, conv_jitter=0.15)
     return mc, H, W, yhat, par
 
 
@@ -33,7 +33,7 @@ def _close(a, b, name):
     assert float(r.max()) <= 1.0, name
 
 
-@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small])
+@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small, wl.config_hop_conv])
 def test_modules_match_oracle(mk):
     from paper_2605_02726_amd.autograd import Modules, arm_rate, synthesis, upsample
     mc, H, W, yhat, par = _case(mk)

@@ -24,6 +24,11 @@ pytestmark = pytest.mark.gpu
 RTOL = 2e-2
 TOT = 1e-3
 
+def _with_conv(mc):
+    mc.ups_conv = 1
+    return mc
+
+
 CASES = {
     "small_random": (wl.config_small, 64, 64, 11, True),
     "hop_128x192_random": (wl.config_hop, 128, 192, 12, True),
@@ -38,6 +43,10 @@ CASES = {
     "MOP_64x128_random": (lambda: wl.config_preset("MOP"), 64, 128, 16, True),
     "HOP_64x128_random": (lambda: wl.config_preset("HOP"), 64, 128, 17, True),
     "VHOP_64x128_random": (lambda: wl.config_preset("VHOP"), 64, 128, 18, True),
+    # upsampling Conv refinement (random taps; identity taps at init)
+    "hop_conv_128x192_random": (wl.config_hop_conv, 128, 192, 20, True),
+    "hop_conv_512x768_init": (wl.config_hop_conv, 512, 768, 2, False),
+    "tiny_conv_64x32_random": (lambda: _with_conv(wl.config_tiny()), 64, 32, 21, True),
 }
 
 
@@ -47,7 +56,7 @@ def _state(case):
     img = wl.image_large(seed) if (H, W) == (512, 768) else wl.synth_image(H, W, seed)
     if rnd:
         lat = wl.random_latents(mc, H, W, seed, scale=2.0)
-        par = wl.init_params(mc, seed, arm_out_zero=False)
+        par = wl.init_params(mc, seed, arm_out_zero=False, conv_jitter=0.15)
     else:
         lat = np.zeros(wl.n_latents(mc, H, W), np.float32)
         par = wl.init_params(mc, seed)

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 SUBS = ("arm", "syn", "ups", "ifce")
 
 
-@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small, wl.config_hop_hyper])
+@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small, wl.config_hop_hyper, wl.config_hop_conv])
 def test_nn_quantize_matches_the_oracle(mk):
     from paper_2605_02726_amd.encoder import Encoder, schedule
     mc = mk()

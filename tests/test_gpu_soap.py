@@ -60,7 +60,7 @@ def _factors(mc, layout, flat):
     return out
 
 
-@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small, wl.config_hop_hyper])
+@pytest.mark.parametrize("mk", [wl.config_hop, wl.config_small, wl.config_hop_hyper, wl.config_hop_conv])
 def test_first_call_sets_factors_and_eigenbases(mk):
     mc, H, W, img, lat, par, seed = _case(mk)
     lam, lr = 1e-3, 1e-2
