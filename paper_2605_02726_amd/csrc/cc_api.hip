@@ -111,10 +111,11 @@ int ups_tile_wgs(const DevDesc& h, int j) {
 // per source grid on the chain levels.
 int ups_bwd_rows(const DevDesc& h, int j) { return j < h.ups_jc ? ups_tile_wgs(h, j) : h.L - j; }
 
-// Workgroups of the Conv refinement's adjoint at level j: one per (channel
-// of T_j, CC_UPC_TILE positions of grid j); none without the refinement.
+// Workgroups of the Conv refinement at level j (forward and adjoint): one
+// per (channel of T_j, CC_UPC_TH x CC_UPC_TW tile of grid j); none without
+// the refinement.
 int upc_wgs(const DevDesc& h, int j) {
-  return h.ups_conv ? cdiv(h.gh[j] * h.gw[j], CC_UPC_TILE) * (h.L - j) : 0;
+  return h.ups_conv ? cdiv(h.gh[j], CC_UPC_TH) * cdiv(h.gw[j], CC_UPC_TW) * (h.L - j) : 0;
 }
 
 int check_config(const cc_config* c, int H, int W) {
@@ -848,9 +849,7 @@ int ups_forward(cc_state* const* s, int n, hipStream_t st) {
   if (lc.tile0[n] > 0) RET(cc_launch_ups_fwd_chain(lc, st));
   for (int j = s[0]->lo.h.L - 1; j >= 1; --j) {
     // Conv refinement: V_j = Conv_j(T_j), the transposed convolution's input
-    const Launch lv = plan(s, n, [j](const DevDesc& h) {
-      return h.ups_conv ? cdiv(h.gh[j] * h.gw[j], CC_PIX_TILE) : 0;
-    });
+    const Launch lv = plan(s, n, [j](const DevDesc& h) { return upc_wgs(h, j); });
     if (lv.tile0[n] > 0) RET(cc_launch_upc_fwd(lv, j, st));
     const Launch l = plan(s, n, [j](const DevDesc& h) {
       return j < h.ups_jc ? cdiv(h.gh[j - 1] * h.gw[j - 1], CC_PIX_TILE) : 0;

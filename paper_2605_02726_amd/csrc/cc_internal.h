@@ -168,7 +168,8 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_FUSED_MAXWG 512  // fused ARM kernel: workgroups per image (each takes every n-th band)
 #endif
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
-#define CC_UPC_TILE 256     // upsampling Conv adjoint: positions per workgroup
+#define CC_UPC_TH 16        // upsampling Conv (forward and adjoint): tile rows
+#define CC_UPC_TW 64        // and columns
 #define CC_UPS_COARSE 2048  // upsampling levels whose output grid has at most this many positions
                             // run as one workgroup per source grid, all such levels in LDS
 #define CC_UPS_CHAIN_T 1024 // threads of those workgroups

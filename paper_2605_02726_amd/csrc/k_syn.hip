@@ -246,6 +246,14 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
 }
 
 // ------------------------------------------------- Conv refinement ----
+// Both kernels take one workgroup (256 threads) per (channel of T_j, tile of
+// CC_UPC_TH x CC_UPC_TW positions of grid j) and stage a window with a 3-wide
+// halo in LDS, every load of a thread issued before the first LDS store.
+constexpr int CTH = CC_UPC_TH, CTW = CC_UPC_TW;
+constexpr int CWH = CTH + 6, CWW = CTW + 6;   // window with the 7-tap halo
+constexpr int NWIN = (CWH * CWW + 255) / 256;
+static_assert(CTW == 64, "the passes index tile columns by lane");
+
 // 7-tap symmetric kernel k[0..6] = (c3 c2 c1 c0 c1 c2 c3) of level j.
 __device__ __forceinline__ void conv_kernel7(const CDesc* d, int j, float* k) {
   const CF* c = (const CF*)(d->theta + d->n_lat + d->p_upc[j]);
@@ -255,36 +263,67 @@ __device__ __forceinline__ void conv_kernel7(const CDesc* d, int j, float* k) {
   k[0] = k[6] = c[3];
 }
 
-// V_j = Conv_j(T_j): one thread per position of grid j, all channels;
-// V[y][x] = sum_a k[a] sum_b k[b] T[clamp(y + a - 3)][clamp(x + b - 3)].
-__global__ __launch_bounds__(CC_PIX_TILE) void k_upc_fwd(Launch L, int j) {
+// Tile of workgroup wgi at level j: channel and top-left corner.
+__device__ __forceinline__ void upc_tile(const CDesc* d, int j, int wgi, int& ch, int& y0, int& x0) {
+  const int ntx = (d->gw[j] + CTW - 1) / CTW, nt = ntx * ((d->gh[j] + CTH - 1) / CTH);
+  ch = wgi / nt;
+  const int t = wgi - ch * nt;
+  y0 = (t / ntx) * CTH;
+  x0 = (t - (t / ntx) * ntx) * CTW;
+}
+
+// win[r][c] = src[clamp(y0 - 3 + r)][clamp(x0 - 3 + c)] (clamped = replicate
+// edge) or, with zero_out, 0 outside the grid.
+__device__ __forceinline__ void load_window(const float* src, int y0, int x0, int hi, int wi,
+                                            bool zero_out, float (*win)[CWW + 1]) {
+  float v[NWIN];
+#pragma unroll
+  for (int u = 0; u < NWIN; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    const int r = i / CWW, c = i - r * CWW;
+    const int y = y0 - 3 + r, x = x0 - 3 + c;
+    const bool in = y >= 0 && y < hi && x >= 0 && x < wi;
+    v[u] = (i < CWH * CWW && (in || !zero_out)) ? src[clampi(y, 0, hi - 1) * wi + clampi(x, 0, wi - 1)]
+                                                : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < NWIN; ++u) {
+    const int i = threadIdx.x + 256 * u;
+    if (i < CWH * CWW) win[i / CWW][i % CWW] = v[u];
+  }
+}
+
+// V_j = Conv_j(T_j): V[y][x] = sum_a k[a] sum_b k[b] T[clamp(y + a - 3)][clamp(x + b - 3)],
+// rows pass into LDS, then the columns pass.
+__global__ __launch_bounds__(256) void k_upc_fwd(Launch L, int j) {
+  __shared__ float win[CWH][CWW + 1];
+  __shared__ float rp[CWH][CTW + 1];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
-  const int hi = d->gh[j], wi = d->gw[j], n = hi * wi;
-  const int p = (blockIdx.x - L.tile0[im]) * CC_PIX_TILE + threadIdx.x;
-  if (p >= n) return;
-  const int y = p / wi, x = p - y * wi;
+  const int hi = d->gh[j], wi = d->gw[j];
+  int ch, y0, x0;
+  upc_tile(d, j, blockIdx.x - L.tile0[im], ch, y0, x0);
   float k[7];
   conv_kernel7(d, j, k);
-  int ry[7], cx[7];
-#pragma unroll
-  for (int a = 0; a < 7; ++a) {
-    ry[a] = clampi(y + a - 3, 0, hi - 1) * wi;
-    cx[a] = clampi(x + a - 3, 0, wi - 1);
-  }
-  const int nch = d->L - j;
-  float* out = d->V + d->voff[j];
-  for (int ch = 0; ch < nch; ++ch) {
-    const float* in = tchan(d, j, ch);
+  load_window(tchan(d, j, ch), y0, x0, hi, wi, false, win);
+  __syncthreads();
+  for (int i = threadIdx.x; i < CWH * CTW; i += 256) {
+    const int r = i >> 6, x = i & 63;
     float s = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      float r = 0.0f;
+    for (int b = 0; b < 7; ++b) s += k[b] * win[r][x + b];
+    rp[r][x] = s;
+  }
+  __syncthreads();
+  float* out = d->V + d->voff[j] + (size_t)ch * hi * wi;
+  for (int i = threadIdx.x; i < CTH * CTW; i += 256) {
+    const int y = i >> 6, x = i & 63;
+    if (y0 + y < hi && x0 + x < wi) {
+      float s = 0.0f;
 #pragma unroll
-      for (int b = 0; b < 7; ++b) r += k[b] * in[ry[a] + cx[b]];
-      s += k[a] * r;
+      for (int a = 0; a < 7; ++a) s += k[a] * rp[y + a][x];
+      out[(y0 + y) * wi + x0 + x] = s;
     }
-    out[(size_t)ch * n + p] = s;
   }
 }
 
@@ -304,74 +343,70 @@ __device__ __forceinline__ void conv_adj_w(const float* k, int i, int n, float* 
   }
 }
 
-// Adjoint of Conv_j: one workgroup per (channel of T_j, CC_UPC_TILE
-// positions of grid j).  dT_j = Conv_j^T(dV_j) goes to the distortion
-// gradient of yhat^(j) (channel 0) or to dU_{j+1}; the tap gradients are
-// sum over outputs o of dV[o] * dV[o]/dc_q, with dV[o]/dc_q the row sums
-// (over b, weighted by k[b]) of the rows a with |a - 3| = q plus the column
-// sums of the columns b with |b - 3| = q.  One partial row of 4 tap gradients
-// per workgroup.
-__global__ __launch_bounds__(CC_UPC_TILE) void k_upc_bwd(Launch L, int j) {
-  __shared__ float sh[4][CC_UPC_TILE / 64];
+// Adjoint of Conv_j.  dT_j = Conv_j^T(dV_j) (columns pass into LDS, then the
+// rows pass) goes to the distortion gradient of yhat^(j) (channel 0) or to
+// dU_{j+1}.  The tap gradient of c_q is the sum over outputs o of dV[o] times
+// (the row-filtered T at rows o_y -+ q plus the column-filtered T at columns
+// o_x -+ q; once for q = 0).  One partial row of 4 tap gradients per workgroup.
+__global__ __launch_bounds__(256) void k_upc_bwd(Launch L, int j) {
+  __shared__ float gw[CWH][CWW + 1];    // dV window, 0 outside the grid
+  __shared__ float tw[CWH][CWW + 1];    // T window, replicate edge
+  __shared__ float c1[CWH][CTW + 1];    // dV through the columns adjoint
+  __shared__ float rt[CWH][CTW + 1];    // T through the row taps
+  __shared__ float ct[CTH][CWW + 1];    // T through the column taps
+  __shared__ float awx[CTW][7], awy[CTH][7];
+  __shared__ float sh[4][4];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
   const int wgi = blockIdx.x - L.tile0[im];
   const int hi = d->gh[j], wi = d->gw[j], n = hi * wi;
-  const int nt = (n + CC_UPC_TILE - 1) / CC_UPC_TILE;
-  const int ch = wgi / nt;
   const int tid = threadIdx.x;
-  const int p = (wgi - ch * nt) * CC_UPC_TILE + tid;
+  int ch, y0, x0;
+  upc_tile(d, j, wgi, ch, y0, x0);
   float k[7];
   conv_kernel7(d, j, k);
+  load_window(d->dV + d->voff[j] + (size_t)ch * n, y0, x0, hi, wi, true, gw);
+  load_window(tchan(d, j, ch), y0, x0, hi, wi, false, tw);
+  if (tid < CTW) conv_adj_w(k, x0 + tid, wi, awx[tid]);
+  else if (tid < CTW + CTH) conv_adj_w(k, y0 + tid - CTW, hi, awy[tid - CTW]);
+  __syncthreads();
+  for (int i = tid; i < CWH * CTW; i += 256) {
+    const int r = i >> 6, x = i & 63;
+    float s = 0.0f, t = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+      s += awx[x][b] * gw[r][x + b];
+      t += k[b] * tw[r][x + b];
+    }
+    c1[r][x] = s;
+    rt[r][x] = t;
+  }
+  for (int i = tid; i < CTH * CWW; i += 256) {
+    const int y = i / CWW, c = i - y * CWW;
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) s += k[a] * tw[y + a][c];
+    ct[y][c] = s;
+  }
+  __syncthreads();
   float dc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  if (p < n) {
-    const int y = p / wi, x = p - y * wi;
-    const float* T = tchan(d, j, ch);
-    const float* G = d->dV + d->voff[j] + (size_t)ch * n;
-    float awy[7], awx[7];
-    conv_adj_w(k, y, hi, awy);
-    conv_adj_w(k, x, wi, awx);
-    float g = 0.0f;
+  for (int i = tid; i < CTH * CTW; i += 256) {
+    const int y = i >> 6, x = i & 63;
+    const int iy = y0 + y, ix = x0 + x;
+    if (iy < hi && ix < wi) {
+      float g = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      const int oy = y + a - 3;
-      if (oy < 0 || oy >= hi) continue;
-      float r = 0.0f;
+      for (int a = 0; a < 7; ++a) g += awy[y][a] * c1[y + a][x];
+      if (ch == 0)
+        d->dyq[d->goff[j] + iy * wi + ix] = g;
+      else
+        d->dU[d->uoff[j + 1] + (size_t)(ch - 1) * n + iy * wi + ix] = g;
+      const float gv = gw[y + 3][x + 3];
+      dc[0] += gv * (rt[y + 3][x] + ct[y][x + 3]);
 #pragma unroll
-      for (int b = 0; b < 7; ++b) {
-        const int ox = x + b - 3;
-        if (ox >= 0 && ox < wi) r += awx[b] * G[oy * wi + ox];
-      }
-      g += awy[a] * r;
+      for (int q = 1; q < 4; ++q)
+        dc[q] += gv * ((rt[y + 3 - q][x] + rt[y + 3 + q][x]) + (ct[y][x + 3 - q] + ct[y][x + 3 + q]));
     }
-    if (ch == 0)
-      d->dyq[d->goff[j] + p] = g;
-    else
-      d->dU[d->uoff[j + 1] + (size_t)(ch - 1) * n + p] = g;
-    int ry[7], cx[7];
-#pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      ry[a] = clampi(y + a - 3, 0, hi - 1) * wi;
-      cx[a] = clampi(x + a - 3, 0, wi - 1);
-    }
-    float rows[7], cols[7];
-#pragma unroll
-    for (int b = 0; b < 7; ++b) cols[b] = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      float r = 0.0f;
-#pragma unroll
-      for (int b = 0; b < 7; ++b) {
-        const float t = T[ry[a] + cx[b]];
-        r += k[b] * t;
-        cols[b] += k[a] * t;
-      }
-      rows[a] = r;
-    }
-    const float gv = G[p];
-    dc[0] = gv * (rows[3] + cols[3]);
-#pragma unroll
-    for (int q = 1; q < 4; ++q) dc[q] = gv * ((rows[3 - q] + rows[3 + q]) + (cols[3 - q] + cols[3 + q]));
   }
   const int wv = tid >> 6, ln = tid & 63;
 #pragma unroll
@@ -381,9 +416,7 @@ __global__ __launch_bounds__(CC_UPC_TILE) void k_upc_bwd(Launch L, int j) {
   }
   __syncthreads();
   if (tid < 4) {
-    float s2 = 0.0f;
-#pragma unroll
-    for (int w = 0; w < CC_UPC_TILE / 64; ++w) s2 += sh[tid][w];
+    const float s2 = (sh[tid][0] + sh[tid][1]) + (sh[tid][2] + sh[tid][3]);
     d->wp[d->prod[d->prod_upc1 + j - 1].off + (size_t)wgi * 4 + tid] = s2;
   }
 }
@@ -1328,11 +1361,11 @@ int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st) {
   return ok();
 }
 int cc_launch_upc_fwd(const Launch& l, int j, hipStream_t st) {
-  hipLaunchKernelGGL(k_upc_fwd, dim3(l.tile0[l.n]), dim3(CC_PIX_TILE), 0, st, l, j);
+  hipLaunchKernelGGL(k_upc_fwd, dim3(l.tile0[l.n]), dim3(256), 0, st, l, j);
   return ok();
 }
 int cc_launch_upc_bwd(const Launch& l, int j, hipStream_t st) {
-  hipLaunchKernelGGL(k_upc_bwd, dim3(l.tile0[l.n]), dim3(CC_UPC_TILE), 0, st, l, j);
+  hipLaunchKernelGGL(k_upc_bwd, dim3(l.tile0[l.n]), dim3(256), 0, st, l, j);
   return ok();
 }
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st) {
