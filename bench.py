@@ -228,6 +228,27 @@ def measure_batch(steps, warmup, precision="bf16", n=16):
     res = {"value": px * steps / dt / 1e6, "unit": "Mpixel-iterations/s", "images": n,
            "megapixels": round(px / 1e6, 3), "ms_per_step": round(1e3 * dt / steps, 4),
            "precision": precision, "steps": steps}
+    # the latent join + Adam kernel over the whole batch (one launch per
+    # step), alone on the chip (branches in order), live HIP-event timing
+    import ctypes as C
+    from paper_2605_02726_amd import _lib
+    from paper_2605_02726_amd.encoder import set_branch_overlap
+    prev = set_branch_overlap(False)
+    L = _lib.lib()
+    _lib.check(L.cc_timing_enable(b"join"))
+    for _ in range(steps):
+        t += 1
+        step_batch(encs, [step_params(t, *schedule(t, 500))] * n, sync=False)
+    torch.cuda.synchronize()
+    ms, cnt = C.c_double(0.0), C.c_int(0)
+    _lib.check(L.cc_timing_read(C.byref(ms), C.byref(cnt)))
+    _lib.check(L.cc_timing_enable(None))
+    set_branch_overlap(prev)
+    jb = sum(hbm_bytes_per_step(mc, e.H, e.W)["join"] for e in encs)
+    js = ms.value / max(cnt.value, 1) / 1e3
+    res["join_adam"] = {"bytes_per_launch": jb, "avg_launch_ms": round(1e3 * js, 4),
+                        "achieved_GBs": round(jb / js / 1e9, 1), "peak_GBs": PEAKS["hbm_GBs"],
+                        "frac": round(jb / js / 1e9 / PEAKS["hbm_GBs"], 4), "branches": "in order"}
     del encs
     return res
 

@@ -77,3 +77,33 @@ def test_conv_taps_follow_the_oracle_over_steps():
     ref = ost.theta[ost.n_lat:][idx]
     print("conv taps", np.max(np.abs(got - ref)), flush=True)
     assert np.allclose(got, ref, rtol=0, atol=1e-5)
+
+
+def test_short_encode_against_the_oracle():
+    """300 iterations of a 128x192 encode from identity taps against the FP64
+    oracle's results (tests/golden/conv_encode_128x192_300.json), with the
+    trajectory criterion of the hyperlatent encode: J within 1%, bits within
+    2%, PSNR within 0.2%."""
+    import json
+    import os
+    from paper_2605_02726_amd.encoder import Encoder, schedule
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "conv_encode_128x192_300.json")))
+    mc = wl.config_hop_conv()
+    H, W, seed, lam, n = 128, 192, 6, 1e-3, gold["n_iter"]
+    enc = Encoder(mc, torch.from_numpy(wl.synth_image(H, W, seed)), lam, seed,
+                  np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, seed),
+                  precision="fp32")
+    for t in range(1, n + 1):
+        enc.step(t, *schedule(t, n), sync=False)
+    rd = enc.rd_eval()
+    ref = gold["conv"]
+    j = rd["mse"] + lam * rd["bits"] / (H * W)
+    jr = ref["mse"] + lam * ref["bits"] / (H * W)
+    taps = enc.get_state()["params"][np.array(wl.conv_taps_offsets(mc))[:, None] + np.arange(4)]
+    print(f"bits {rd['bits']:.1f} vs {ref['bits']:.1f}, psnr {rd['psnr']:.4f} vs {ref['psnr']:.4f}, "
+          f"J {j:.6f} vs {jr:.6f} ({j / jr - 1:+.2e}); taps max diff "
+          f"{np.max(np.abs(taps - np.array(gold['conv_taps']))):.2e}", flush=True)
+    assert abs(j / jr - 1.0) <= 1e-2
+    assert rd["bits"] == pytest.approx(ref["bits"], rel=2e-2)
+    assert rd["psnr"] == pytest.approx(ref["psnr"], rel=2e-3)
