@@ -275,8 +275,10 @@ int cc_syn_bwd(cc_state* s, const float* grad_xhat, float* grad_zhat, float* gra
 /* Launch shape of the tunable kernels of a state (for an autotuner; the
  * results differ only by the order of the weight-gradient partial sums):
  *   arm_wgs            fused ARM workgroups per image, 1 .. the number of
- *                      2-row bands of all grids (each workgroup takes every
- *                      arm_wgs-th band);
+ *                      2-row bands of all grids; the bands are packed onto
+ *                      them longest first, each onto the least loaded one
+ *                      (default: the fewest workgroups whose loads stay at
+ *                      the largest band's, at most 512);
  *   syn_chunks_per_wg  64-pixel chunks per synthesis-backward workgroup,
  *                      4 .. 64;
  *   res_tiles_per_wg   8 x 64 tiles per residual-adjoint workgroup, 1 .. 16.

@@ -28,7 +28,7 @@ from .encoder import Encoder, schedule
 
 SYN_CHUNKS = (6, 8, 12, 16, 24)
 RES_TILES = (1, 2, 4)
-ARM_FRACTIONS = (1.0, 0.75, 0.5)
+ARM_FRACTIONS = (1.0, 0.85, 0.7)   # of the library's packed default; one band per workgroup too
 
 
 def size_bucket(H: int, W: int) -> str:
@@ -66,16 +66,17 @@ class ShapeCache:
 
 
 def _time_steps(enc: Encoder, t0: int, n: int, warmup: int = 2) -> float:
-    """Milliseconds per step over n steps after warmup steps."""
+    """Milliseconds per step over n steps after warmup steps (the schedules
+    of a 1,000-iteration encode, repeated if the tuner runs longer)."""
     t = t0
     for _ in range(warmup):
         t += 1
-        enc.step(t, *schedule(t, 1000), sync=False)
+        enc.step(t, *schedule(1 + (t - 1) % 1000, 1000), sync=False)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(n):
         t += 1
-        enc.step(t, *schedule(t, 1000), sync=False)
+        enc.step(t, *schedule(1 + (t - 1) % 1000, 1000), sync=False)
     stop.record()
     stop.synchronize()
     return start.elapsed_time(stop) / n
@@ -102,8 +103,9 @@ def tune(mc, H: int, W: int, precision: str = "bf16", steps: int = 8, seed: int 
     knobs = [("syn_chunks_per_wg", SYN_CHUNKS), ("res_tiles_per_wg", RES_TILES)]
     if precision == "bf16" and _lib.lib().cc_arm_fused_available(C.byref(enc.cfg)):
         # the plain ARM runs one workgroup per chunk; only the fused form has this knob
-        arm = sorted({max(1, min(bands, int(round(f * info["arm_wgs"])))) for f in ARM_FRACTIONS},
-                     reverse=True)
+        arm = {max(1, min(bands, int(round(f * info["arm_wgs"])))) for f in ARM_FRACTIONS}
+        arm.add(min(bands, 512))
+        arm = sorted(arm, reverse=True)
         knobs.insert(0, ("arm_wgs", arm))
     for knob, cands in knobs:
         for c in cands:

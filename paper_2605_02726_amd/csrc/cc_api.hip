@@ -10,6 +10,8 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <queue>
+#include <utility>
 #include <vector>
 
 #include "cc_internal.h"
@@ -69,8 +71,9 @@ struct Layout {
   size_t bytes = 0;
   size_t off_desc = 0, off_img, off_theta, off_m, off_v, off_grad, off_yhat, off_dq, off_dyd,
          off_dyq, off_dc, off_df, off_U, off_dU, off_V, off_dV, off_X, off_dXa, off_dXb, off_wp, off_wp2,
-         off_agt, off_sgt, off_lpb, off_lpm, off_scal, off_aft;
+         off_agt, off_sgt, off_lpb, off_lpm, off_scal, off_aft, off_abl, off_awb;
   std::vector<unsigned> arm_gtab, syn_gtab, arm_ftab;
+  std::vector<int> arm_blist, arm_wbeg;
   std::vector<int> soap_tab;
   std::vector<unsigned char> nnq_group;
   size_t off_ngrp = 0, off_nkeep = 0, off_nbits = 0;
@@ -96,6 +99,60 @@ int ups_chain_first(const DevDesc& h) {
   int jc = h.L;
   while (jc > 1 && h.gh[jc - 2] * h.gw[jc - 2] <= CC_UPS_COARSE) --jc;
   return jc;
+}
+
+// Bands of the fused ARM kernel (CC_FUSED_BAND rows of one grid, grid 0's
+// first) packed onto nw workgroups, longest first, each onto the least
+// loaded workgroup (LPT).  A band's load is its positions plus a fixed
+// per-band cost (staging, merges).  blist: bands grouped by workgroup, in
+// ascending order within a workgroup; wbeg: nw + 1 offsets.  Returns the
+// largest load.
+constexpr long long ARM_BAND_COST = 256;
+long long arm_pack(const DevDesc& h, int nw, std::vector<int>& blist, std::vector<int>& wbeg) {
+  std::vector<std::pair<long long, int>> bands;   // (-load, band)
+  for (int k = 0, b = 0; k < h.NG; ++k)
+    for (int y = 0; y < h.gh[k]; y += CC_FUSED_BAND, ++b)
+      bands.push_back({-((long long)std::min(CC_FUSED_BAND, h.gh[k] - y) * h.gw[k] + ARM_BAND_COST), b});
+  std::sort(bands.begin(), bands.end());
+  std::priority_queue<std::pair<long long, int>, std::vector<std::pair<long long, int>>,
+                      std::greater<std::pair<long long, int>>> heap;
+  for (int w = 0; w < nw; ++w) heap.push({0, w});
+  std::vector<std::vector<int>> per(nw);
+  long long mx = 0;
+  for (const auto& b : bands) {
+    auto top = heap.top();
+    heap.pop();
+    top.first -= b.first;
+    per[top.second].push_back(b.second);
+    mx = std::max(mx, top.first);
+    heap.push(top);
+  }
+  blist.clear();
+  wbeg.assign(1, 0);
+  for (auto& v : per) {
+    std::sort(v.begin(), v.end());
+    blist.insert(blist.end(), v.begin(), v.end());
+    wbeg.push_back((int)blist.size());
+  }
+  return mx;
+}
+
+// Default fused-ARM workgroups per image: the fewest whose packing keeps
+// every workgroup's load at the largest band's (so the kernel lasts one
+// largest band while leaving the other compute units to the distortion
+// branch), at most CC_FUSED_MAXWG.
+int arm_default_wgs(const DevDesc& h) {
+  long long tot = 0, big = 0;
+  for (int k = 0; k < h.NG; ++k)
+    for (int y = 0; y < h.gh[k]; y += CC_FUSED_BAND) {
+      const long long c = (long long)std::min(CC_FUSED_BAND, h.gh[k] - y) * h.gw[k] + ARM_BAND_COST;
+      tot += c;
+      big = std::max(big, c);
+    }
+  std::vector<int> bl, wb;
+  int nw = (int)std::max<long long>(1, (tot + big - 1) / big);
+  while (nw < std::min(h.arm_nwg_fused, CC_FUSED_MAXWG) && arm_pack(h, nw, bl, wb) > big) ++nw;
+  return std::min(nw, CC_FUSED_MAXWG);
 }
 
 // Tiles of the residual-layer adjoint.
@@ -310,7 +367,8 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.nprod = q;
   h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
   h.prod[h.prod_arm].nrows = h.arm_nwg;
-  h.arm_wgs = std::min(h.arm_nwg_fused, CC_FUSED_MAXWG);
+  h.arm_wgs = arm_default_wgs(h);
+  arm_pack(h, h.arm_wgs, Lo.arm_blist, Lo.arm_wbeg);
 
   // weight-gradient tables: (index into gradient vector, index into
   // activation vector, grid requirement) per parameter, matching the LDS row
@@ -552,6 +610,8 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   Lo.off_sgt = take(sizeof(unsigned) * Lo.syn_gtab.size());
   Lo.off_lpb = take(sizeof(double) * (size_t)std::max(h.arm_nwg_plain, h.arm_nwg_fused));
   Lo.off_aft = take(sizeof(unsigned) * (size_t)h.n_arm_par);
+  Lo.off_abl = take(sizeof(int) * (size_t)h.arm_nwg_fused);
+  Lo.off_awb = take(sizeof(int) * (size_t)(h.arm_nwg_fused + 1));
   Lo.off_lpm = take(sizeof(double) * (size_t)h.pix_ntile);
   Lo.off_scal = take(sizeof(double) * 4);
   Lo.off_stab = take(sizeof(int) * Lo.soap_tab.size());
@@ -589,6 +649,8 @@ void set_pointers(Layout& Lo, char* base) {
   h.wp2 = (double*)(base + Lo.off_wp2);
   h.arm_gtab = (unsigned*)(base + Lo.off_agt);
   h.arm_ftab = (unsigned*)(base + Lo.off_aft);
+  h.arm_blist = (int*)(base + Lo.off_abl);
+  h.arm_wbeg = (int*)(base + Lo.off_awb);
   h.syn_gtab = (unsigned*)(base + Lo.off_sgt);
   h.lp_bits = (double*)(base + Lo.off_lpb);
   h.lp_mse = (double*)(base + Lo.off_lpm);
@@ -1068,6 +1130,8 @@ int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, doub
   if (e == hipSuccess) e = cp(h.arm_gtab, s->lo.arm_gtab.data(), sizeof(unsigned) * s->lo.arm_gtab.size());
   if (e == hipSuccess) e = cp(h.syn_gtab, s->lo.syn_gtab.data(), sizeof(unsigned) * s->lo.syn_gtab.size());
   if (e == hipSuccess) e = cp(h.arm_ftab, s->lo.arm_ftab.data(), sizeof(unsigned) * s->lo.arm_ftab.size());
+  if (e == hipSuccess) e = cp(h.arm_blist, s->lo.arm_blist.data(), sizeof(int) * s->lo.arm_blist.size());
+  if (e == hipSuccess) e = cp(h.arm_wbeg, s->lo.arm_wbeg.data(), sizeof(int) * s->lo.arm_wbeg.size());
   if (e == hipSuccess) e = cp(h.soap_tab, s->lo.soap_tab.data(), sizeof(int) * s->lo.soap_tab.size());
   if (e == hipSuccess) e = cp(h.nnq_group, s->lo.nnq_group.data(), s->lo.nnq_group.size());
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1467,7 +1531,14 @@ int cc_set_launch_shape(cc_state* s, int arm_wgs, int syn_chunks_per_wg, int res
   // no step of this state may still read the descriptor (the side stream's
   // work joins back into the caller's stream, so this waits for it too)
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
-  if (arm_wgs > 0) h.arm_wgs = arm_wgs;
+  if (arm_wgs > 0) {
+    h.arm_wgs = arm_wgs;
+    arm_pack(h, h.arm_wgs, s->lo.arm_blist, s->lo.arm_wbeg);
+    HIPCHK(hipMemcpy(h.arm_blist, s->lo.arm_blist.data(), sizeof(int) * s->lo.arm_blist.size(),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h.arm_wbeg, s->lo.arm_wbeg.data(), sizeof(int) * s->lo.arm_wbeg.size(),
+                     hipMemcpyHostToDevice));
+  }
   if (syn_chunks_per_wg > 0) {
     h.syn_cpw = syn_chunks_per_wg;
     h.syn_nwg = cdiv(h.syn_nchunk, h.syn_cpw);

@@ -56,7 +56,7 @@ struct DevDesc {
   int arm_nchunk, arm_nwg, syn_nchunk, syn_nwg, pix_nwg, nprod;
   int lat_ntile, pix_ntile, res_nwg;
   int ups_jc;                   // first upsampling level run by the per-source chain kernels (L: none)
-  int arm_wgs;                  // fused ARM: workgroups per image (each takes every arm_wgs-th band)
+  int arm_wgs;                  // fused ARM: workgroups per image (bands packed by the host)
   int syn_cpw, res_tpw;         // synthesis chunks / residual tiles per workgroup (launch shape)
   ProdSeg prod[CC_MAX_PROD];
   int prod_arm, prod_syn, prod_res0, prod_ups1, prod_upc1;   // producer indices
@@ -66,6 +66,8 @@ struct DevDesc {
   double* wp2;
   unsigned* arm_gtab;
   unsigned* arm_ftab;           // fused ARM: parameter -> (grid, accumulator, row, column)
+  // fused ARM: bands of workgroup w are arm_blist[arm_wbeg[w] .. arm_wbeg[w + 1])
+  int *arm_blist, *arm_wbeg;
   int arm_nwg_plain, arm_nwg_fused, arm_fused;  // arm_fused: planes A/B hold the rate gradient
   unsigned* syn_gtab;
   double *lp_bits, *lp_mse, *scal;

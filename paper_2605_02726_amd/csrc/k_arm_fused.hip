@@ -159,7 +159,6 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
   const int wg = blockIdx.x - Lc.tile0[im];
-  const int nwg = Lc.tile0[im + 1] - Lc.tile0[im];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, n = lane & 31, hh = lane >> 5;
   const CF* P = (const CF*)(d->theta + d->n_lat);
   const CF* W3 = P + d->p_aw[2];
@@ -215,13 +214,14 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   }
   const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
   const float bs0 = stab ? P[d->p_asb] : 0.0f, bs1 = stab ? P[d->p_asb + 1] : 0.0f;
-  int nbt = 0;
-  for (int kk = 0; kk < d->NG; ++kk) nbt += (d->gh[kk] + TH - 1) / TH;
-
-  // bands wg, wg + nwg, ... of this image (grid 0's bands first, then grid
-  // 1's, ...); every band writes its own partial row and bits partial, so the
-  // results do not depend on the number of workgroups
-  for (int bidx = wg; bidx < nbt; bidx += nwg) {
+  // this workgroup's bands (band index: grid 0's bands first, then grid
+  // 1's, ...), packed by the host so that the workgroups' loads are even;
+  // every band writes its own partial row and bits partial, so the results
+  // do not depend on the packing
+  const int e0 = __builtin_amdgcn_readfirstlane(d->arm_wbeg[wg]);
+  const int e1 = __builtin_amdgcn_readfirstlane(d->arm_wbeg[wg + 1]);
+  for (int e = e0; e < e1; ++e) {
+  const int bidx = __builtin_amdgcn_readfirstlane(d->arm_blist[e]);
   int k = 0, band = bidx;
   for (;;) {
     const int nb = (d->gh[k] + TH - 1) / TH;
