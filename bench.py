@@ -38,7 +38,7 @@ PEAKS = {
 # calibration (FETCH x2.000, WRITE x1.000); the commands and the table are in
 # profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
 # until the counters are taken again.
-ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3585.1 + 1.0 * 18675.9) * 1024)
+ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3608.5 + 1.0 * 18671.7) * 1024)
 
 
 def arm_flops_per_step(mc, H, W):
@@ -277,7 +277,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="both", choices=["both", "fp32", "bf16"])
-    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=36, help="oracle steps for cpu_baseline (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=20, help="batched-step timing (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving trace length (0 = skip)")
     ap.add_argument("--serve-iters", type=int, default=2000)
