@@ -36,7 +36,7 @@ def size_bucket(H: int, W: int) -> str:
 
 
 def cache_key(mc, precision: str, H: int, W: int, device: Optional[str] = None) -> str:
-    dev = device if device is not None else torch.cuda.get_device_name(0)
+    dev = device if device is not None else torch.cuda.get_device_name(torch.cuda.current_device())
     shape = json.dumps(mc.as_dict(), sort_keys=True)
     return f"{dev}|{precision}|{shape}|{size_bucket(H, W)}"
 

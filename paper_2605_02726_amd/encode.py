@@ -59,10 +59,8 @@ class GpuBackend:
 
     def create(self, seed, params):
         from .encoder import Encoder
-        _, H, W = self.image.shape
-        n_lat = sum((H >> k) * (W >> k) for k in range(self.mc.L))
-        return Encoder(self.mc, self.image, self.lam, seed, np.zeros(n_lat, np.float32), params,
-                       precision=self.precision)
+        # latents start at zero (every grid, hyperlatent grids included)
+        return Encoder(self.mc, self.image, self.lam, seed, None, params, precision=self.precision)
 
     def step_batch(self, handles, specs):
         """specs: list of (t, lr, T, sigma, quant, update_latents)."""

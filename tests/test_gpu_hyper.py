@@ -61,3 +61,25 @@ def test_hyper_batch_equals_alone(precision):
         sa, sb = a.get_state(), b.get_state()
         for k in ("latents", "params", "m", "v"):
             assert np.array_equal(sa[k], sb[k]), k
+
+
+@pytest.mark.parametrize("mk", [wl.config_hop_hyper, wl.config_hop_conv])
+def test_multi_stage_driver_on_the_gpu(mk):
+    """The multi-stage driver (warm-up candidates in one batch, main stage,
+    hard-round stage with frozen latents) with the hyperlatent and the Conv
+    refinement decoders: latents sized by the library (hyperlatent grids
+    included), every stage runs, and the final cost is below the best
+    warm-up cost."""
+    from paper_2605_02726_amd.encode import GpuBackend, StagePlan, encode
+    mc = mk()
+    H, W = 64, 128
+    img = wl.synth_image(H, W, 71)
+    be = GpuBackend(mc, img, 1e-3, precision="bf16")
+    plan = StagePlan(candidates=(3, 2), warmup_iters=20, main_iters=60, hard_iters=10)
+    res = encode(be, [wl.init_params(mc, 80 + i) for i in range(3)], plan)
+    assert res.handle.n_lat == wl.n_latents(mc, H, W)
+    stages = [h["stage"] for h in res.history]
+    assert stages == ["warm-up", "warm-up", "main", "hard"]
+    first = res.history[0]["costs"]
+    print("warm-up costs", first, "final", res.rd, flush=True)
+    assert res.rd["loss"] < min(first)
