@@ -53,6 +53,8 @@ CASES = {
     "hop_conv_128x192_random": (wl.config_hop_conv, 128, 192, 20, True),
     "hop_conv_512x768_init": (wl.config_hop_conv, 512, 768, 2, False),
     "tiny_conv_64x32_random": (lambda: _with_conv(wl.config_tiny()), 64, 32, 21, True),
+    # both: hyperlatent grids and the Conv refinement
+    "hop_hyper_conv_128x192_random": (lambda: _with_conv(wl.config_hop_hyper()), 128, 192, 22, True),
 }
 
 
