@@ -170,9 +170,9 @@ int ups_bwd_rows(const DevDesc& h, int j) { return j < h.ups_jc ? ups_tile_wgs(h
 
 // Workgroups of the Conv refinement at level j (forward and adjoint): one
 // per (channel of T_j, CC_UPC_TH x CC_UPC_TW tile of grid j); none without
-// the refinement.
+// the refinement or on the chain levels (the chain kernels include it).
 int upc_wgs(const DevDesc& h, int j) {
-  return h.ups_conv ? cdiv(h.gh[j], CC_UPC_TH) * cdiv(h.gw[j], CC_UPC_TW) * (h.L - j) : 0;
+  return h.ups_conv && j < h.ups_jc ? cdiv(h.gh[j], CC_UPC_TH) * cdiv(h.gw[j], CC_UPC_TW) * (h.L - j) : 0;
 }
 
 int check_config(const cc_config* c, int H, int W) {
@@ -338,8 +338,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.prod_arm = q;
   h.prod[q++] = {0, h.n_arm_par, h.arm_nwg, 0, wpo};
   wpo += (long long)std::max(h.arm_nwg_plain, h.arm_nwg_fused) * h.n_arm_par;
-  // the chain kernels have no Conv refinement: with it every level is tiled
-  h.ups_jc = h.ups_conv ? h.L : ups_chain_first(h);
+  h.ups_jc = ups_chain_first(h);
   h.prod_ups1 = q;
   for (int j = 1; j < h.L; ++j) {
     const int rows = ups_bwd_rows(h, j);
@@ -348,7 +347,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   }
   h.prod_upc1 = q;
   for (int j = 1; h.ups_conv && j < h.L; ++j) {
-    const int rows = upc_wgs(h, j);
+    const int rows = j < h.ups_jc ? upc_wgs(h, j) : h.L - j;   // tiles, or one per source
     h.prod[q++] = {h.p_upc[j], 4, rows, 0, wpo};
     wpo += (long long)rows * 4;
   }

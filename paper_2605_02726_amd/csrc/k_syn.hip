@@ -475,6 +475,26 @@ __device__ __forceinline__ void adj_weights(const float* h, float (*wa)[8], int 
   }
 }
 
+// Conv refinement passes of the chain kernels (h x w <= CC_UPS_COARSE / 4):
+// rows R[y][x] = sum_b k[b] A[y][clamp(x + b - 3)], columns
+// B[y][x] = sum_a k[a] R[clamp(y + a - 3)][x].
+__device__ __forceinline__ void conv_rows(const float* k, const float* A, float* R, int h, int w) {
+  CC_FOR2D(h, w, y, x) {
+    float s = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) s += k[b] * A[y * w + clampi(x + b - 3, 0, w - 1)];
+    R[y * w + x] = s;
+  }
+}
+__device__ __forceinline__ void conv_cols(const float* k, const float* R, float* B, int h, int w) {
+  CC_FOR2D(h, w, y, x) {
+    float s = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) s += k[a] * R[clampi(y + a - 3, 0, h - 1) * w + x];
+    B[y * w + x] = s;
+  }
+}
+
 __global__ __launch_bounds__(CT) void k_ups_fwd_chain(Launch L) {
   __shared__ float bufA[CC_UPS_COARSE], bufB[CC_UPS_COARSE], rw[CC_UPS_COARSE / 2];
   const int im = cc_find_img(L, blockIdx.x);
@@ -491,16 +511,30 @@ __global__ __launch_bounds__(CT) void k_ups_fwd_chain(Launch L) {
     const int hi = d->gh[j], wi = d->gw[j], ho = d->gh[j - 1], wo = d->gw[j - 1];
     const CF* hc = (const CF*)(d->theta + d->n_lat + d->p_ups[j]);
     const float h[4] = {hc[0], hc[1], hc[2], hc[3]};
+    const bool conv = d->ups_conv != 0;
     __syncthreads();
-    rows_pass(h, A, rw, hi, wi, wo);
+    const float* src = A;   // the transposed convolution's input
+    if (conv) {
+      float k7[7];
+      conv_kernel7(d, j, k7);
+      conv_rows(k7, A, rw, hi, wi);
+      __syncthreads();
+      conv_cols(k7, rw, B, hi, wi);
+      __syncthreads();
+      src = B;
+    }
+    rows_pass(h, src, rw, hi, wi, wo);
     __syncthreads();
-    cols_pass(h, rw, B, hi, ho, wo);
+    float* dst = conv ? A : B;
+    cols_pass(h, rw, dst, hi, ho, wo);
     __syncthreads();
     float* out = d->U + d->uoff[j] + (size_t)(g - j) * ho * wo;
-    for (int i = threadIdx.x; i < ho * wo; i += CT) out[i] = B[i];
-    float* t = A;
-    A = B;
-    B = t;
+    for (int i = threadIdx.x; i < ho * wo; i += CT) out[i] = dst[i];
+    if (!conv) {
+      float* t = A;
+      A = B;
+      B = t;
+    }
   }
 }
 
@@ -509,6 +543,10 @@ __global__ __launch_bounds__(CT) void k_ups_bwd_chain(Launch L) {
   __shared__ float tin[CC_UPS_COARSE / 4], rc[CC_UPS_COARSE / 2], rf[CC_UPS_COARSE / 2],
       cf[CC_UPS_COARSE / 2];
   __shared__ float wxa[CC_UPS_COARSE / 4][8], wya[CC_UPS_COARSE / 4][8];
+  // Conv refinement: T through the Conv's row taps and column taps, V_j,
+  // d V_j and the columns adjoint of d V_j
+  __shared__ float crt[CC_UPS_COARSE / 4], cct[CC_UPS_COARSE / 4], vin[CC_UPS_COARSE / 4],
+      dvb[CC_UPS_COARSE / 4], ctmp[CC_UPS_COARSE / 4];
   __shared__ float sh[4][CW];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
@@ -530,9 +568,21 @@ __global__ __launch_bounds__(CT) void k_ups_bwd_chain(Launch L) {
       const float* ts = tchan(d, j, g - j);
       for (int i = tid; i < hi * wi; i += CT) tin[i] = ts[i];
     }
+    const bool conv = d->ups_conv != 0;
+    float k7[7];
+    if (conv) conv_kernel7(d, j, k7);
     adj_weights(h, wxa, wi, wo);
     adj_weights(h, wya, hi, ho);
     __syncthreads();
+    const float* tsrc = tin;   // the transposed convolution's input
+    if (conv) {
+      conv_rows(k7, tin, crt, hi, wi);
+      conv_cols(k7, tin, cct, hi, wi);
+      __syncthreads();
+      conv_cols(k7, crt, vin, hi, wi);
+      __syncthreads();
+      tsrc = vin;
+    }
     // column adjoint of G: rc[oy][ix] over the outputs ox = 2 ix - 3 + b
     CC_FOR2D(ho, wi, oy, ix) {
       float a = 0.0f;
@@ -543,14 +593,14 @@ __global__ __launch_bounds__(CT) void k_ups_bwd_chain(Launch L) {
       }
       rc[oy * wi + ix] = a;
     }
-    rows_pass(h, tin, rf, hi, wi, wo);   // rf[iy][ox]: T through the row taps
+    rows_pass(h, tsrc, rf, hi, wi, wo);   // rf[iy][ox]: T through the row taps
     // cf[oy][ix]: T through the column taps
     CC_FOR2D(ho, wi, oy, ix) {
       int ty[4], iy[4];
       out_taps(oy, hi, ty, iy);
       float s = 0.0f;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) s += tapv(h, ty[a]) * tin[iy[a] * wi + ix];
+      for (int a = 0; a < 4; ++a) s += tapv(h, ty[a]) * tsrc[iy[a] * wi + ix];
       cf[oy * wi + ix] = s;
     }
     __syncthreads();
@@ -562,8 +612,12 @@ __global__ __launch_bounds__(CT) void k_ups_bwd_chain(Launch L) {
         const int oy = 2 * iy - 3 + b;
         a += wya[iy][b] * rc[clampi(oy, 0, ho - 1) * wi + ix];
       }
-      D[iy * wi + ix] = a;
-      if (j == g) d->dyq[d->goff[g] + iy * wi + ix] = a;
+      if (conv) {
+        dvb[iy * wi + ix] = a;
+      } else {
+        D[iy * wi + ix] = a;
+        if (j == g) d->dyq[d->goff[g] + iy * wi + ix] = a;
+      }
     }
     // tap gradients: every output o contributes G[o] times the derivative of
     // U[o] in each tap, through the row taps (rf) and the column taps (cf)
@@ -594,6 +648,53 @@ __global__ __launch_bounds__(CT) void k_ups_bwd_chain(Launch L) {
       for (int w2 = 0; w2 < CW; ++w2) s2 += sh[tid][w2];
       const long long pg_off = d->prod[d->prod_ups1 + j - 1].off;
       d->wp[pg_off + (size_t)(g - j) * 4 + tid] = s2;
+    }
+    if (conv) {
+      // adjoint of the Conv (columns of the filter, then rows) into D, and
+      // its tap gradients from T's row- and column-filtered copies
+      __syncthreads();
+      CC_FOR2D(hi, wi, y, x) {
+        float aw[7];
+        conv_adj_w(k7, x, wi, aw);
+        float s = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 7; ++b) {
+          const int ox = x + b - 3;
+          if (ox >= 0 && ox < wi) s += aw[b] * dvb[y * wi + ox];
+        }
+        ctmp[y * wi + x] = s;
+      }
+      __syncthreads();
+      float dc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      CC_FOR2D(hi, wi, y, x) {
+        float aw[7];
+        conv_adj_w(k7, y, hi, aw);
+        float s = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+          const int oy = y + a - 3;
+          if (oy >= 0 && oy < hi) s += aw[a] * ctmp[oy * wi + x];
+        }
+        D[y * wi + x] = s;
+        if (j == g) d->dyq[d->goff[g] + y * wi + x] = s;
+        const float gv = dvb[y * wi + x];
+        dc[0] += gv * (crt[y * wi + x] + cct[y * wi + x]);
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+          dc[q] += gv * ((crt[clampi(y - q, 0, hi - 1) * wi + x] + crt[clampi(y + q, 0, hi - 1) * wi + x]) +
+                         (cct[y * wi + clampi(x - q, 0, wi - 1)] + cct[y * wi + clampi(x + q, 0, wi - 1)]));
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float s2 = wave_sum(dc[q]);
+        if (ln == 0) sh[q][wv] = s2;
+      }
+      __syncthreads();
+      if (tid < 4) {
+        float s2 = 0.0f;
+        for (int w2 = 0; w2 < CW; ++w2) s2 += sh[tid][w2];
+        d->wp[d->prod[d->prod_upc1 + j - 1].off + (size_t)(g - j) * 4 + tid] = s2;
+      }
     }
     float* t = G;
     G = D;

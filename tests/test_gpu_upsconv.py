@@ -1,8 +1,7 @@
 """The upsampling Conv refinement on the GPU: with identity taps it computes
-the plain upsampling (same totals; gradients within the FP32 rule, since
-every level then runs the tiled kernels, which sum in another order than the
-coarse-level chain kernels); a batch equals each state alone, bitwise; the
-Conv tap gradients follow the oracle over a few steps of Adam."""
+the plain upsampling (same totals; gradients within the FP32 rule); a batch
+equals each state alone, bitwise; the Conv tap gradients follow the oracle
+over a few steps of Adam; a 300-iteration encode follows the oracle's."""
 import numpy as np
 import pytest
 import torch
