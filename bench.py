@@ -28,8 +28,8 @@ PEAKS = {
     # MI355X published peaks
     "hbm_GBs": 8000.0,
     "bf16_mfma_TFLOPs": 2500.0,
-    # FP32 vector FMA without packed-FP32 instructions (which this build
-    # disables): 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+    # FP32 vector FMA without packed-FP32 instructions (the library is
+    # compiled without them): 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
     "fp32_valu_TFLOPs": 78.6,
 }
 
@@ -301,7 +301,7 @@ def main():
         args.serve_requests = 0
         args.cpu_steps = 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the per-image encode step is "
+        print(json.dumps({"error": "the benchmark runs on one GPU: the per-image encode step is "
                           "data-parallel inside one MI355X; --gpus must be 1"}))
         sys.exit(2)
 
