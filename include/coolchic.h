@@ -291,6 +291,16 @@ int cc_set_launch_shape(cc_state* s, int arm_wgs, int syn_chunks_per_wg, int res
 int cc_get_launch_shape(const cc_state* s, int* arm_wgs, int* syn_chunks_per_wg,
                         int* res_tiles_per_wg, int* arm_bands);
 
+/* How the fused ARM splits an image's bands over nw workgroups (host only,
+ * no GPU needed): *nbands = number of 2-row bands of all grids (band index:
+ * grid 0's bands from the top, then grid 1's, ...), *default_nw = the
+ * default workgroup count of a state of this shape; with wbeg (nw + 1 ints)
+ * and blist (*nbands ints) also the packing itself: workgroup w takes the
+ * bands blist[wbeg[w] .. wbeg[w + 1]).  Any pointer may be NULL; nw is read
+ * only when wbeg or blist is given (CC_EINVAL outside [1, *nbands]). */
+int cc_arm_band_plan(const cc_config* cfg, int H, int W, int nw, int* nbands, int* default_nw,
+                     int* wbeg, int* blist);
+
 /* Live kernel timing for measurement tools: HIP events are recorded on the
  * launch stream around every launch of one kernel class ("arm", "syn_bwd",
  * "res_bwd", "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which

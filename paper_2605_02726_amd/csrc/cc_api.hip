@@ -1077,6 +1077,25 @@ size_t cc_state_bytes(const cc_config* cfg, int H, int W) {
   return lo.bytes;
 }
 
+int cc_arm_band_plan(const cc_config* cfg, int H, int W, int nw, int* nbands, int* default_nw,
+                     int* wbeg, int* blist) {
+  int rc = check_config(cfg, H, W);
+  if (rc != CC_OK) return rc;
+  Layout lo;
+  build_layout(cfg, H, W, lo);
+  const DevDesc& h = lo.h;
+  if (nbands) *nbands = h.arm_nwg_fused;
+  if (default_nw) *default_nw = h.arm_wgs;
+  if (!wbeg && !blist) return CC_OK;
+  if (nw < 1 || nw > h.arm_nwg_fused)
+    return fail(CC_EINVAL, "nw=%d outside [1, %d]", nw, h.arm_nwg_fused);
+  std::vector<int> bl, wb;
+  arm_pack(h, nw, bl, wb);
+  if (wbeg) memcpy(wbeg, wb.data(), sizeof(int) * wb.size());
+  if (blist) memcpy(blist, bl.data(), sizeof(int) * bl.size());
+  return CC_OK;
+}
+
 int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, double lambda,
                   uint64_t seed, const float* init_latents_host, const float* init_params_host,
                   void* mem, size_t bytes, void* stream, cc_state** out) {

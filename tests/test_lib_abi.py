@@ -101,3 +101,39 @@ def test_fused_arm_covers_the_workload_and_the_presets(lib):
                *[lambda n=n: wl.config_preset(n) for n in ("LOP", "MOP", "HOP", "VHOP")]):
         cfg = lib.make_config(mk(), lib.CC_BF16_FUSED)
         assert L.cc_arm_fused_available(C.byref(cfg)) == 1
+
+
+@pytest.mark.parametrize("mk,H,W", [(wl.config_hop, 512, 768), (wl.config_hop_hyper, 512, 768),
+                                    (wl.config_hop, 2048, 2048), (wl.config_small, 64, 64),
+                                    (wl.config_hop, 320, 1088)])
+def test_arm_band_packing(lib, mk, H, W):
+    """Every band on exactly one workgroup, ascending within a workgroup, no
+    workgroup empty; the packing (longest first onto the least loaded) keeps
+    the largest load within one band of the even share, and the default
+    workgroup count keeps it at the largest band's (unless capped at 512)."""
+    mc = mk()
+    cfg = lib.make_config(mc, lib.CC_BF16_FUSED)
+    nb, nd = C.c_int(0), C.c_int(0)
+    assert lib.lib().cc_arm_band_plan(C.byref(cfg), H, W, 0, C.byref(nb), C.byref(nd), None, None) == 0
+    levels = wl.grid_levels(mc)
+    loads = []
+    for k in levels:
+        h, w = H >> k, W >> k
+        loads += [min(2, h - y) * w + 256 for y in range(0, h, 2)]
+    assert nb.value == len(loads)
+    big = max(loads)
+    for nw in sorted({1, 7, nd.value, nb.value, max(1, nb.value // 3)}):
+        wbeg = (C.c_int * (nw + 1))()
+        blist = (C.c_int * nb.value)()
+        assert lib.lib().cc_arm_band_plan(C.byref(cfg), H, W, nw, None, None, wbeg, blist) == 0
+        assert wbeg[0] == 0 and wbeg[nw] == nb.value
+        assert sorted(blist) == list(range(nb.value))
+        per = [list(blist[wbeg[i]:wbeg[i + 1]]) for i in range(nw)]
+        assert all(p and p == sorted(p) for p in per)
+        mx = max(sum(loads[b] for b in p) for p in per)
+        assert mx <= sum(loads) / nw + big
+        if nw == nd.value and nw < 512:
+            assert mx <= big
+    with pytest.raises(AssertionError):
+        assert lib.lib().cc_arm_band_plan(C.byref(cfg), H, W, nb.value + 1, None, None,
+                                          (C.c_int * (nb.value + 2))(), None) == 0
