@@ -82,6 +82,28 @@ def _time_steps(enc: Encoder, t0: int, n: int, warmup: int = 2) -> float:
     return start.elapsed_time(stop) / n
 
 
+def search(start: dict, knobs, measure, min_gain: float = 0.01):
+    """Coordinate descent: for each (knob, candidates) in turn, time every
+    candidate with the other knobs at the best values so far (``measure``:
+    shape -> ms); a candidate replaces the best only when faster by more than
+    ``min_gain``.  Returns (best shape, its ms, the start's ms, trials)."""
+    best = dict(start)
+    best_ms = measure(best)
+    start_ms = best_ms
+    trials = [(dict(best), best_ms)]
+    for knob, cands in knobs:
+        for c in cands:
+            if c == best[knob]:
+                continue
+            trial = dict(best)
+            trial[knob] = c
+            ms = measure(trial)
+            trials.append((dict(trial), ms))
+            if ms < best_ms * (1.0 - min_gain):
+                best, best_ms = trial, ms
+    return best, best_ms, start_ms, trials
+
+
 def tune(mc, H: int, W: int, precision: str = "bf16", steps: int = 8, seed: int = 0,
          cache: Optional[ShapeCache] = None, min_gain: float = 0.01) -> dict:
     """Fastest launch shape found for this decoder, precision and image size;
@@ -93,32 +115,21 @@ def tune(mc, H: int, W: int, precision: str = "bf16", steps: int = 8, seed: int 
                   precision=precision)
     info = enc.launch_shape()
     bands = info.pop("arm_bands")
-    best = dict(info)
-    t = 0
-    enc.set_launch_shape(**best)
-    best_ms = _time_steps(enc, t, steps)
-    t += steps + 2
-    default_ms = best_ms
-    trials = [(dict(best), best_ms)]
     knobs = [("syn_chunks_per_wg", SYN_CHUNKS), ("res_tiles_per_wg", RES_TILES)]
     if precision == "bf16" and _lib.lib().cc_arm_fused_available(C.byref(enc.cfg)):
         # the plain ARM runs one workgroup per chunk; only the fused form has this knob
         arm = {max(1, min(bands, int(round(f * info["arm_wgs"])))) for f in ARM_FRACTIONS}
         arm.add(min(bands, 512))
-        arm = sorted(arm, reverse=True)
-        knobs.insert(0, ("arm_wgs", arm))
-    for knob, cands in knobs:
-        for c in cands:
-            if c == best[knob]:
-                continue
-            trial = dict(best)
-            trial[knob] = c
-            enc.set_launch_shape(**trial)
-            ms = _time_steps(enc, t, steps)
-            t += steps + 2
-            trials.append((dict(trial), ms))
-            if ms < best_ms * (1.0 - min_gain):
-                best, best_ms = trial, ms
+        knobs.insert(0, ("arm_wgs", sorted(arm, reverse=True)))
+    clock = {"t": 0}
+
+    def measure(shape):
+        enc.set_launch_shape(**shape)
+        ms = _time_steps(enc, clock["t"], steps)
+        clock["t"] += steps + 2
+        return ms
+
+    best, best_ms, default_ms, trials = search(info, knobs, measure, min_gain)
     del enc
     if cache is not None:
         cache.put(mc, precision, H, W, best, best_ms)

@@ -37,3 +37,24 @@ def test_shape_cache_round_trip(tmp_path):
     m = at.ShapeCache(None)
     m.put(mc, "bf16", 64, 64, shape, 1.0, "dev")
     assert m.get(mc, "bf16", 64, 64, "dev") == shape
+
+
+def test_search_is_coordinate_descent_with_a_minimum_gain():
+    # separable cost: the best value of each knob wins when it gains > 1%
+    cost = {"a": {1: 1.0, 2: 0.9, 3: 0.95}, "b": {10: 0.5, 20: 0.496, 30: 0.3}}
+    calls = []
+
+    def measure(shape):
+        calls.append(dict(shape))
+        return cost["a"][shape["a"]] + cost["b"][shape["b"]]
+    best, ms, start_ms, trials = at.search({"a": 1, "b": 10}, [("a", (1, 2, 3)), ("b", (10, 20, 30))],
+                                           measure, min_gain=0.01)
+    assert best == {"a": 2, "b": 30}
+    assert start_ms == 1.5 and abs(ms - 1.2) < 1e-12
+    # the start once, then every other candidate of a knob with the others at their best
+    assert calls == [{"a": 1, "b": 10}, {"a": 2, "b": 10}, {"a": 3, "b": 10},
+                     {"a": 2, "b": 20}, {"a": 2, "b": 30}]
+    assert len(trials) == len(calls)
+    # a gain below min_gain keeps the earlier shape
+    best, _, _, _ = at.search({"a": 1, "b": 10}, [("b", (20,))], measure, min_gain=0.01)
+    assert best == {"a": 1, "b": 10}
