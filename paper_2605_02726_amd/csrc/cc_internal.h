@@ -170,6 +170,9 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_FUSED_MAXWG 512  // fused ARM kernel: workgroups per image (each takes every n-th band)
 #endif
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
+#ifndef CC_SYN_BWD_WAVES
+#define CC_SYN_BWD_WAVES 8   // waves per synthesis-backward workgroup (4 or 8)
+#endif
 #define CC_UPC_TH 16        // upsampling Conv (forward and adjoint): tile rows
 #define CC_UPC_TW 64        // and columns
 #define CC_UPS_COARSE 2048  // upsampling levels whose output grid has at most this many positions

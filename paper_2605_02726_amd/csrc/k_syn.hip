@@ -918,24 +918,29 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_syn_fwd(Launch Lc, int final_ms
   if (final_mse) mse_epilogue(d, p, valid, out, wgi, sh);
 }
 
-// Backward of a one-hidden-layer trunk.  The four waves of a workgroup take
-// the same 64 pixels and a quarter of the hidden units each: a wave
-// recomputes its units' pre-activations, back-propagates the output gradient
-// through them, accumulates its units' weight gradients in registers (one
-// partial per lane, summed over the workgroup's chunks) and leaves its share
-// of dzhat in LDS, where the four shares are added in a fixed order.  The
-// per-lane partials are reduced once at the end (LDS transpose, then a fixed
-// butterfly), giving one partial row per workgroup.
-template <int W1>
-__global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
+// Backward of a one-hidden-layer trunk.  The NWV waves of a workgroup take
+// the same 64 pixels and 1/NWV of the hidden units each: a wave recomputes
+// its units' pre-activations, back-propagates the output gradient through
+// them, accumulates its units' weight gradients in registers (one partial
+// per lane, summed over the workgroup's chunks) and leaves its share of dzhat
+// in LDS, where the NWV shares are added in a fixed order.  The per-lane
+// partials are reduced once at the end (LDS transpose, then a fixed
+// butterfly), giving one partial row per workgroup.  Eight waves halve the
+// accumulators per wave, so four waves fit on a SIMD instead of two.
+template <int W1, int NWV>
+__global__ __launch_bounds__(NWV * 64, 2) void k_syn_bwd1(Launch Lc, int src_b) {
+  static_assert(NWV == 4 || NWV == 8, "four or eight waves");
   using S = SynLds<1, W1, 0>;
-  constexpr int UPW = (W1 + 3) / 4;       // hidden units per wave
+  constexpr int UPW = (W1 + NWV - 1) / NWV;   // hidden units per wave
+  constexpr int QPW = 8 / NWV;                // dzhat channels per wave
+  constexpr int NF = (11 + NWV - 1) / NWV;    // chunk features loaded per wave
   constexpr int NU = UPW * 12;           // unit accumulators: dW1 row (8), db1, dWo column (3)
-  constexpr int NACC = NU + 9;           // + stabilizer dWs[c][q] for 2 q's, output bias
+  constexpr int NACC = NU + 3 * QPW + 3;  // + stabilizer dWs[c][q] for the wave's q's, output bias
   constexpr int RS = 16 * 65;            // reduction region per wave
+  constexpr int NRED = 2 * NWV * 8 * 64 > NWV * RS ? 2 * NWV * 8 * 64 : NWV * RS;
   __shared__ __align__(16) float w[S::TOTAL];
   __shared__ __align__(16) float zb[2][64][12];      // per lane: z[0..7], go[0..2]
-  __shared__ __align__(16) float red[4 * RS];        // dz shares [2][4][8][64], then reduction
+  __shared__ __align__(16) float red[NRED];          // dz shares [2][NWV][8][64], then reduction
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
   const int wg = blockIdx.x - Lc.tile0[im];
@@ -946,14 +951,14 @@ __global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
   const float* G = src_b ? d->dXb : d->dXa;
   stage_syn_weights<1, W1, 0>(d, (const CF*)(d->theta + d->n_lat), w);
 
-  // feature f of a chunk (f = wv + 4j): 0 yhat, 1..7 U planes (zero beyond L),
-  // 8..10 output-gradient planes
-  float pre[3];
+  // feature f of a chunk (f = wv + NWV j): 0 yhat, 1..7 U planes (zero
+  // beyond L), 8..10 output-gradient planes
+  float pre[NF];
   auto load_chunk = [&](int ch) {
     const int p = ch * CC_SYN_CHUNK + lane;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int f = wv + 4 * j;
+    for (int j = 0; j < NF; ++j) {
+      const int f = wv + NWV * j;
       float v = 0.0f;
       if (p < n) {
         if (f == 0)
@@ -968,8 +973,8 @@ __global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int f = wv + 4 * j;
+    for (int j = 0; j < NF; ++j) {
+      const int f = wv + NWV * j;
       if (f < 11) zb[buf][lane][f] = pre[j];
     }
   };
@@ -997,7 +1002,7 @@ __global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
 #pragma unroll
     for (int u = 0; u < UPW; ++u) {
       const int a = wv * UPW + u;
-      if (UPW * 4 != W1 && a >= W1) continue;
+      if (UPW * NWV != W1 && a >= W1) continue;
       const float4 r0 = w4[3 * a], r1 = w4[3 * a + 1], r2 = w4[3 * a + 2];
       const float wr[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
       float s = r2.x;
@@ -1015,20 +1020,21 @@ __global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
       acc[12 * u + 10] += go[1] * h;
       acc[12 * u + 11] += go[2] * h;
     }
-    float* dzs = red + buf * (4 * 8 * 64);
+    float* dzs = red + buf * (NWV * 8 * 64);
 #pragma unroll
     for (int q = 0; q < 8; ++q) dzs[(wv * 8 + q) * 64 + lane] = dz[q];
     if (nxt < nchunk) store_chunk(buf ^ 1);
     __syncthreads();
-    // dzhat channels q = wv and wv + 4: the four shares in wave order, plus the
+    // dzhat channels q = wv + NWV qi: the NWV shares in wave order, plus the
     // stabilizer's term
     const int p = ch * CC_SYN_CHUNK + lane;
 #pragma unroll
-    for (int qi = 0; qi < 2; ++qi) {
-      const int q = wv + 4 * qi;
+    for (int qi = 0; qi < QPW; ++qi) {
+      const int q = wv + NWV * qi;
       if (q >= L) continue;
-      float v = dzs[(0 * 8 + q) * 64 + lane] + dzs[(1 * 8 + q) * 64 + lane] +
-                dzs[(2 * 8 + q) * 64 + lane] + dzs[(3 * 8 + q) * 64 + lane];
+      float v = dzs[(0 * 8 + q) * 64 + lane];
+#pragma unroll
+      for (int sw = 1; sw < NWV; ++sw) v += dzs[(sw * 8 + q) * 64 + lane];
       v += w[S::TAIL + q] * go[0] + w[S::TAIL + 8 + q] * go[1] + w[S::TAIL + 16 + q] * go[2];
       if (p < n) {
         if (q == 0)
@@ -1040,7 +1046,7 @@ __global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
       for (int c = 0; c < 3; ++c) acc[NU + 3 * qi + c] += go[c] * z[q];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[NU + 6 + c] += go[c];
+    for (int c = 0; c < 3; ++c) acc[NU + 3 * QPW + c] += go[c];
   }
 
   // per-lane partials -> one value per parameter, in a fixed order
@@ -1074,11 +1080,11 @@ __global__ __launch_bounds__(256, 2) void k_syn_bwd1(Launch Lc, int src_b) {
           else
             dst = d->p_sw[1] + (e - 9) * W1 + a;
         }
-      } else if (k < NU + 6) {
-        const int x = k - NU, q = wv + 4 * (x / 3), c = x % 3;
+      } else if (k < NU + 3 * QPW) {
+        const int x = k - NU, q = wv + NWV * (x / 3), c = x % 3;
         if (d->syn_stab && q < L) dst = d->p_ssw + c * L + q;
       } else if (wv == 0) {
-        const int c = k - NU - 6;
+        const int c = k - NU - 3 * QPW;
         dst = d->p_sb[1] + c;
         if (d->syn_stab) dst2 = d->p_ssb + c;
       }
@@ -1447,7 +1453,8 @@ int cc_launch_syn_bwd_plain(const Launch& l, const DevDesc& h, int src_b, hipStr
 #define X(a, b, c)                                                                           \
   if (h.n_syn_hidden == a && h.syn_w[1] == b && w2 == c) {                                   \
     if constexpr (a == 1)                                                                    \
-      hipLaunchKernelGGL((k_syn_bwd1<b>), dim3(l.tile0[l.n]), dim3(256), 0, st, l, src_b);   \
+      hipLaunchKernelGGL((k_syn_bwd1<b, CC_SYN_BWD_WAVES>), dim3(l.tile0[l.n]),               \
+                         dim3(CC_SYN_BWD_WAVES * 64), 0, st, l, src_b);                        \
     else                                                                                     \
       hipLaunchKernelGGL((k_syn_bwd<a, b, c>), dim3(l.tile0[l.n]), dim3(64), 0, st, l, src_b); \
     return ok();                                                                             \
