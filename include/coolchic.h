@@ -277,8 +277,7 @@ int cc_syn_bwd(cc_state* s, const float* grad_xhat, float* grad_zhat, float* gra
  *   arm_wgs            fused ARM workgroups per image, 1 .. the number of
  *                      2-row bands of all grids; the bands are packed onto
  *                      them longest first, each onto the least loaded one
- *                      (default: the fewest workgroups whose loads stay at
- *                      the largest band's, at most 512);
+ *                      (default: one band per workgroup, at most 512);
  *   syn_chunks_per_wg  64-pixel chunks per synthesis-backward workgroup,
  *                      4 .. 64;
  *   res_tiles_per_wg   8 x 64 tiles per residual-adjoint workgroup, 1 .. 16.

@@ -137,23 +137,13 @@ long long arm_pack(const DevDesc& h, int nw, std::vector<int>& blist, std::vecto
   return mx;
 }
 
-// Default fused-ARM workgroups per image: the fewest whose packing keeps
-// every workgroup's load at the largest band's (so the kernel lasts one
-// largest band while leaving the other compute units to the distortion
-// branch), at most CC_FUSED_MAXWG.
-int arm_default_wgs(const DevDesc& h) {
-  long long tot = 0, big = 0;
-  for (int k = 0; k < h.NG; ++k)
-    for (int y = 0; y < h.gh[k]; y += CC_FUSED_BAND) {
-      const long long c = (long long)std::min(CC_FUSED_BAND, h.gh[k] - y) * h.gw[k] + ARM_BAND_COST;
-      tot += c;
-      big = std::max(big, c);
-    }
-  std::vector<int> bl, wb;
-  int nw = (int)std::max<long long>(1, (tot + big - 1) / big);
-  while (nw < std::min(h.arm_nwg_fused, CC_FUSED_MAXWG) && arm_pack(h, nw, bl, wb) > big) ++nw;
-  return std::min(nw, CC_FUSED_MAXWG);
-}
+// Default fused-ARM workgroups per image: one per band, at most
+// CC_FUSED_MAXWG (larger images pack several bands per workgroup).  Fewer
+// workgroups (each grid-0 band alone, the coarser bands grouped) leave
+// compute units to the distortion branch while the ARM runs; they are a
+// tuning choice: they lengthen the kernel, and the overlapped step gained
+// from them only while the distortion branch was the longer one.
+int arm_default_wgs(const DevDesc& h) { return std::min(h.arm_nwg_fused, CC_FUSED_MAXWG); }
 
 // Tiles of the residual-layer adjoint.
 int res_tiles(const DevDesc& h) { return cdiv(h.H, CC_RES_TH) * cdiv(h.W, CC_RES_TW); }

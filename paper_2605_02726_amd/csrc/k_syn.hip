@@ -1274,13 +1274,81 @@ __device__ __forceinline__ int srcs(int q, int o, int n, int* ps) {
 // the clamped reads' contributions.  Weight-gradient partials stay in
 // registers per lane and are reduced once, in a fixed order.
 // src_b selects the input buffer; the output goes to the other.
-__global__ __launch_bounds__(256, 2) void k_res_bwd(Launch Lc, int r, int src_b) {
+// Two groups of four waves take every pixel of the tile: group 0 owns the
+// weight-gradient entries [0, RG) and the input channel 0 of the adjoint,
+// group 1 the entries [RG, 84) and the input channels 1, 2, which halves the
+// per-lane accumulators (four waves per SIMD instead of two); the layer's
+// weights are read through scalar loads.  A lane of either group sees the
+// pixels a lane of a four-wave workgroup would.
+constexpr int RG = 48;   // weight-gradient entries of group 0
+
+template <int Q0, int NQ, int C0, int NC>
+__device__ __forceinline__ void res_bwd_pixel(const float (*xs)[CC_RES_TH + 2][CC_RES_TW + 2],
+                                              const float (*gs)[CC_RES_TH + 2][CC_RES_TW + 2],
+                                              const CF* Wr, float* acc, int ly, int lx,
+                                              int y, int x, int H, int W, int ty0, int tx0,
+                                              float* O, int n) {
+  float g[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g[c] = gs[c][ly + 1][lx + 1];
+  // weight gradient: g[co] * X_r[ci] at the tap's clamped position (entry
+  // q = (co 3 + ci) 9 + t), and the bias g[co] (entry 81 + co)
+#pragma unroll
+  for (int q = Q0; q < Q0 + NQ; ++q) {
+    if (q < 81) {
+      const int co = q / 27, ci = (q / 9) % 3, t = q % 9;
+      acc[q - Q0] += g[co] * xs[ci][ly + t / 3][lx + t % 3];
+    } else {
+      acc[q - Q0] += g[q - 81];
+    }
+  }
+  // adjoint, input channels C0 .. C0 + NC - 1 (not interleaved with the
+  // weight-gradient loop: that would hold both loops' LDS values at once)
+  __builtin_amdgcn_sched_barrier(0);
+  float o[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) o[c] = g[C0 + c];
+  if (y > 0 && y < H - 1 && x > 0 && x < W - 1) {
+#pragma unroll
+    for (int co = 0; co < 3; ++co)
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const float gv = gs[co][ly + 2 - t / 3][lx + 2 - t % 3];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) o[c] += Wr[(co * 3 + C0 + c) * 9 + t] * gv;
+      }
+  } else {
+    for (int ky = 0; ky < 3; ++ky) {
+      int py[2];
+      const int cy = srcs(y, ky - 1, H, py);
+      for (int kx = 0; kx < 3; ++kx) {
+        int px[2];
+        const int cx = srcs(x, kx - 1, W, px);
+        const int t = ky * 3 + kx;
+        for (int a2 = 0; a2 < cy; ++a2)
+          for (int b2 = 0; b2 < cx; ++b2) {
+            const int sy = py[a2] - ty0 + 1, sx = px[b2] - tx0 + 1;
+#pragma unroll
+            for (int co = 0; co < 3; ++co) {
+              const float gv = gs[co][sy][sx];
+#pragma unroll
+              for (int c = 0; c < NC; ++c) o[c] += Wr[(co * 3 + C0 + c) * 9 + t] * gv;
+            }
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) O[(size_t)(C0 + c) * n + y * W + x] = o[c];
+}
+
+__global__ __launch_bounds__(512, 4) void k_res_bwd(Launch Lc, int r, int src_b) {
   constexpr int TH = CC_RES_TH, TW = CC_RES_TW, SH = TH + 2, SW = TW + 2;
+  constexpr int NT = 512;
   __shared__ float xs[3][SH][SW];
   __shared__ float gs[3][SH][SW];
-  __shared__ __align__(16) float wadj[3][9][4];   // [ci][tap][co]
-  __shared__ float red[4 * 16 * 65];
-  __shared__ float wsum[4][84];
+  __shared__ float red[8 * 16 * 65];
+  __shared__ float wsum[8][RG];
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
   const int wgi = blockIdx.x - Lc.tile0[im];
@@ -1288,28 +1356,25 @@ __global__ __launch_bounds__(256, 2) void k_res_bwd(Launch Lc, int r, int src_b)
   const int H = d->H, W = d->W, n = H * W;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = wv >> 2, wq = wv & 3;   // group, wave within the group
   const CF* Wr = (const CF*)(d->theta + d->n_lat + d->p_rw[r]);
   const float* G = src_b ? d->dXb : d->dXa;
   float* O = src_b ? d->dXa : d->dXb;
   const float* X = d->X + (size_t)r * 3 * n;
-  if (tid < 108) {
-    const int ci = tid / 36, t = (tid / 4) % 9, co = tid & 3;
-    wadj[ci][t][co] = co < 3 ? Wr[(co * 3 + ci) * 9 + t] : 0.0f;
-  }
-  float acc[84];
+  float acc[RG];
 #pragma unroll
-  for (int q = 0; q < 84; ++q) acc[q] = 0.0f;
+  for (int q = 0; q < RG; ++q) acc[q] = 0.0f;
   const int ntx = (W + TW - 1) / TW, nty = (H + TH - 1) / TH;
   for (int tile = wgi; tile < ntx * nty; tile += nwg) {
     const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * TW;
     // stage X_r (replicate-clamped halo) and the incoming gradient (zero
     // halo): every load of the thread is issued before the first LDS store,
     // so their latencies overlap
-    constexpr int NST = (SH * SW + 255) / 256;
+    constexpr int NST = (SH * SW + NT - 1) / NT;
     float xv[NST][3], gv[NST][3];
 #pragma unroll
     for (int u = 0; u < NST; ++u) {
-      const int i = tid + 256 * u;
+      const int i = tid + NT * u;
       const int ly = i / SW, lx = i - ly * SW;
       const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
       const int cy = clampi(gy, 0, H - 1), cx = clampi(gx, 0, W - 1);
@@ -1320,10 +1385,10 @@ __global__ __launch_bounds__(256, 2) void k_res_bwd(Launch Lc, int r, int src_b)
         gv[u][c] = in ? G[(size_t)c * n + gy * W + gx] : 0.0f;
       }
     }
-    __syncthreads();   // previous tile's reads are done (and wadj is written)
+    __syncthreads();   // previous tile's reads are done
 #pragma unroll
     for (int u = 0; u < NST; ++u) {
-      const int i = tid + 256 * u;
+      const int i = tid + NT * u;
       if (i < SH * SW) {
         const int ly = i / SW, lx = i - ly * SW;
 #pragma unroll
@@ -1336,68 +1401,25 @@ __global__ __launch_bounds__(256, 2) void k_res_bwd(Launch Lc, int r, int src_b)
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < TH / 4; ++k) {
-      const int ly = wv + 4 * k, lx = lane;
+      const int ly = wq + 4 * k, lx = lane;
       const int y = ty0 + ly, x = tx0 + lx;
       if (y >= H || x >= W) continue;
-      float g[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) g[c] = gs[c][ly + 1][lx + 1];
-      // weight gradient: g[co] * X_r[ci] at the tap's clamped position
-#pragma unroll
-      for (int ci = 0; ci < 3; ++ci)
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-          const float v = xs[ci][ly + t / 3][lx + t % 3];
-#pragma unroll
-          for (int co = 0; co < 3; ++co) acc[(co * 3 + ci) * 9 + t] += g[co] * v;
-        }
-#pragma unroll
-      for (int co = 0; co < 3; ++co) acc[81 + co] += g[co];
-      // adjoint
-      float o[3] = {g[0], g[1], g[2]};
-      if (y > 0 && y < H - 1 && x > 0 && x < W - 1) {
-#pragma unroll
-        for (int co = 0; co < 3; ++co)
-#pragma unroll
-          for (int t = 0; t < 9; ++t) {
-            const float gv = gs[co][ly + 2 - t / 3][lx + 2 - t % 3];
-#pragma unroll
-            for (int ci = 0; ci < 3; ++ci) o[ci] += wadj[ci][t][co] * gv;
-          }
-      } else {
-        for (int ky = 0; ky < 3; ++ky) {
-          int py[2];
-          const int cy = srcs(y, ky - 1, H, py);
-          for (int kx = 0; kx < 3; ++kx) {
-            int px[2];
-            const int cx = srcs(x, kx - 1, W, px);
-            const int t = ky * 3 + kx;
-            for (int a2 = 0; a2 < cy; ++a2)
-              for (int b2 = 0; b2 < cx; ++b2) {
-                const int sy = py[a2] - ty0 + 1, sx = px[b2] - tx0 + 1;
-#pragma unroll
-                for (int co = 0; co < 3; ++co) {
-                  const float gv = gs[co][sy][sx];
-#pragma unroll
-                  for (int ci = 0; ci < 3; ++ci) o[ci] += wadj[ci][t][co] * gv;
-                }
-              }
-          }
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) O[(size_t)c * n + y * W + x] = o[c];
+      if (grp == 0)
+        res_bwd_pixel<0, RG, 0, 1>(xs, gs, Wr, acc, ly, lx, y, x, H, W, ty0, tx0, O, n);
+      else
+        res_bwd_pixel<RG, 84 - RG, 1, 2>(xs, gs, Wr, acc, ly, lx, y, x, H, W, ty0, tx0, O, n);
     }
   }
   // per-lane partials -> per-wave sums (LDS transpose, fixed butterfly) ->
-  // workgroup sum in wave order
+  // the group's sum in wave order
   __syncthreads();
   float* rw = red + wv * (16 * 65);
+  const int nq = grp == 0 ? RG : 84 - RG;
 #pragma unroll
-  for (int r0 = 0; r0 < 84; r0 += 16) {
+  for (int r0 = 0; r0 < RG; r0 += 16) {
 #pragma unroll
     for (int k = 0; k < 16; ++k)
-      if (r0 + k < 84) rw[k * 65 + lane] = acc[r0 + k];
+      if (r0 + k < RG) rw[k * 65 + lane] = acc[r0 + k];
     __syncthreads();
     const int pk = lane >> 2, qr = lane & 3;
     float v = 0.0f;
@@ -1406,12 +1428,14 @@ __global__ __launch_bounds__(256, 2) void k_res_bwd(Launch Lc, int r, int src_b)
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
     __syncthreads();
-    if (qr == 0 && r0 + pk < 84) wsum[wv][r0 + pk] = v;
+    if (qr == 0 && r0 + pk < nq) wsum[wv][r0 + pk] = v;
   }
   __syncthreads();
   if (tid < 84) {
+    const int g2 = tid < RG ? 0 : 4, q = tid < RG ? tid : tid - RG;
     const long long pg_off = d->prod[d->prod_res0 + r].off;
-    d->wp[pg_off + (size_t)wgi * 84 + tid] = wsum[0][tid] + wsum[1][tid] + wsum[2][tid] + wsum[3][tid];
+    d->wp[pg_off + (size_t)wgi * 84 + tid] =
+        wsum[g2][q] + wsum[g2 + 1][q] + wsum[g2 + 2][q] + wsum[g2 + 3][q];
   }
 }
 
@@ -1494,6 +1518,6 @@ int cc_launch_res_fwd(const Launch& l, int r, int last, int want_mse, hipStream_
   return ok();
 }
 int cc_launch_res_bwd2(const Launch& l, int r, int src_b, hipStream_t st) {
-  hipLaunchKernelGGL(k_res_bwd, dim3(l.tile0[l.n]), dim3(CC_PIX_TILE), 0, st, l, r, src_b);
+  hipLaunchKernelGGL(k_res_bwd, dim3(l.tile0[l.n]), dim3(512), 0, st, l, r, src_b);
   return ok();
 }

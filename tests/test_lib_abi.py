@@ -109,8 +109,8 @@ def test_fused_arm_covers_the_workload_and_the_presets(lib):
 def test_arm_band_packing(lib, mk, H, W):
     """Every band on exactly one workgroup, ascending within a workgroup, no
     workgroup empty; the packing (longest first onto the least loaded) keeps
-    the largest load within one band of the even share, and the default
-    workgroup count keeps it at the largest band's (unless capped at 512)."""
+    the largest load within one band of the even share; by default one band
+    per workgroup (at most 512 workgroups)."""
     mc = mk()
     cfg = lib.make_config(mc, lib.CC_BF16_FUSED)
     nb, nd = C.c_int(0), C.c_int(0)
@@ -133,7 +133,8 @@ def test_arm_band_packing(lib, mk, H, W):
         mx = max(sum(loads[b] for b in p) for p in per)
         assert mx <= sum(loads) / nw + big
         if nw == nd.value and nw < 512:
-            assert mx <= big
+            assert nw == nb.value and mx <= big
+    assert nd.value == min(nb.value, 512)
     with pytest.raises(AssertionError):
         assert lib.lib().cc_arm_band_plan(C.byref(cfg), H, W, nb.value + 1, None, None,
                                           (C.c_int * (nb.value + 2))(), None) == 0
