@@ -310,6 +310,9 @@ int cc_arm_band_plan(const cc_config* cfg, int H, int W, int nw, int* nbands, in
  * Process-wide, not thread-safe. */
 int cc_timing_enable(const char* kernel);
 int cc_timing_read(double* total_ms, int* count);
+/* Time one launch in n of the enabled class (default 1, every launch), to
+ * keep the events' own cost small in a timed loop; CC_EINVAL for n < 1. */
+int cc_timing_every(int n);
 
 void cc_free_state(cc_state* s);
 const char* cc_last_error(void);

@@ -62,6 +62,7 @@ _PROTOS = [
     ("cc_n_latents", C.c_int64, [C.POINTER(cc_config), C.c_int, C.c_int]),
     ("cc_n_params", C.c_int, [C.POINTER(cc_config)]),
     ("cc_state_bytes", C.c_size_t, [C.POINTER(cc_config), C.c_int, C.c_int]),
+    ("cc_timing_every", C.c_int, [C.c_int]),
     ("cc_arm_band_plan", C.c_int, [C.POINTER(cc_config), C.c_int, C.c_int, C.c_int,
                                    C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p, C.c_void_p]),
     ("cc_init_state", C.c_int, [C.POINTER(cc_config), C.c_int, C.c_int, C.c_void_p, C.c_double,

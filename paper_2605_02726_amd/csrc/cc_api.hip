@@ -773,6 +773,8 @@ int quantise(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st)
 enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_RES_BWD = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6 };
 struct Timing {
   int kind = TK_NONE;
+  int every = 1;                // time one launch in `every`
+  long long seen = 0;           // launches of the kind since enabling
   std::vector<hipEvent_t> ev;   // pairs (start, stop)
   size_t used = 0;
 };
@@ -783,6 +785,8 @@ struct TimeScope {
   bool on;
   hipEvent_t e1 = nullptr;
   TimeScope(int kind, hipStream_t s) : st(s), on(g_timing.kind == kind) {
+    if (!on) return;
+    on = g_timing.seen++ % g_timing.every == 0;
     if (!on) return;
     if (g_timing.used + 2 > g_timing.ev.size()) {
       for (int i = 0; i < 64; ++i) {
@@ -1639,6 +1643,12 @@ int cc_timing_enable(const char* kernel) {
   else if (kernel && kernel[0]) return fail(CC_EINVAL, "unknown kernel class '%s'", kernel);
   g_timing.kind = k;
   g_timing.used = 0;
+  g_timing.seen = 0;
+  return CC_OK;
+}
+int cc_timing_every(int n) {
+  if (n < 1) return fail(CC_EINVAL, "n=%d", n);
+  g_timing.every = n;
   return CC_OK;
 }
 
