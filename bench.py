@@ -38,7 +38,7 @@ PEAKS = {
 # calibration (FETCH x2.000, WRITE x1.000); the commands and the table are in
 # profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
 # until the counters are taken again.
-ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3608.5 + 1.0 * 18671.7) * 1024)
+ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3609.9 + 1.0 * 18674.8) * 1024)
 
 
 def arm_flops_per_step(mc, H, W):
