@@ -39,6 +39,11 @@ PEAKS = {
 # profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
 # until the counters are taken again.
 ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3609.9 + 1.0 * 18674.8) * 1024)
+# Wave-level VALU instructions and MFMA-busy fraction per launch of the same
+# kernel (SQ_INSTS_VALU, MfmaUtil), from the counter pass in
+# profiles/mfma_valu_activity_bf16_512x768.txt; None when the kernel changes.
+ARM_FUSED_VALU_INSTS = 1.748e7
+ARM_FUSED_MFMA_UTIL = 0.0398
 
 
 def arm_flops_per_step(mc, H, W):
@@ -376,6 +381,14 @@ def main():
                 "traffic": ARM_FUSED_TRAFFIC_BYTES if head == "bf16" else None,
                 "traffic_unit": "bytes per launch", "avg_launch_ms": round(1e3 * avg_s, 4),
                 "flops_per_launch": flops}
+        if head == "bf16" and ARM_FUSED_VALU_INSTS:
+            # what bounds it instead: the vector pipes issue a wave-level
+            # instruction every 4 cycles per SIMD (256 CUs x 4 SIMDs, 2.4 GHz)
+            valu_s = ARM_FUSED_VALU_INSTS * 4 / (256 * 4 * 2.4e9)
+            roof["issue"] = {"valu_insts_per_launch": ARM_FUSED_VALU_INSTS,
+                             "valu_issue_frac": round(valu_s / avg_s, 4),
+                             "mfma_busy_frac": ARM_FUSED_MFMA_UTIL,
+                             "note": "counters: profiles/mfma_valu_activity_bf16_512x768.txt"}
         if "arm_avg_ms" in serial:
             a1 = flops / (serial["arm_avg_ms"] / 1e3) / 1e12
             roof["kernel_alone"] = {"achieved": round(a1, 3), "frac": round(a1 / peak, 5),
