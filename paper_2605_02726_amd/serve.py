@@ -91,6 +91,9 @@ class Server:
             if self.shapes is not None:
                 shape = self.shapes.get(self.mc, self.precision, H, W)
                 if shape is not None:
+                    # a bucket spans sizes: a smaller image may have fewer ARM bands
+                    bands = enc.launch_shape()["arm_bands"]
+                    shape["arm_wgs"] = min(int(shape.get("arm_wgs", 0)), bands)
                     enc.set_launch_shape(**shape)
             self.used += enc.nbytes
             self.peak_used = max(self.peak_used, self.used)

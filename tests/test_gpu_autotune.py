@@ -113,3 +113,11 @@ def test_tune_caches_a_valid_shape_and_the_server_applies_it(tmp_path):
     got = srv.active[0][1].launch_shape()
     got.pop("arm_bands")
     assert got == shape
+    # a smaller image of the same size bucket has fewer ARM bands: the cached
+    # workgroup count is clamped to them
+    cache.put(mc, "bf16", 256, 256, dict(shape, arm_wgs=10 ** 6), 1.0)
+    srv.submit(Job(rid=1, image=wl.synth_image(192, 128, 6), lam=1e-3, seed=6, n_iter=3,
+                   params=wl.init_params(mc, 6)))
+    srv._admit()
+    small = srv.active[1][1].launch_shape()
+    assert small["arm_wgs"] == small["arm_bands"]
