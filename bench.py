@@ -135,7 +135,33 @@ def _measure_step(precision, steps, warmup, timing, optimizer, nn_quantize, hype
     return out
 
 
-def hbm_bytes_per_step(mc, H, W):
+def reduction_pass_bytes(mc, H, W, syn_cpw=12, res_tpw=1):
+    """Bytes of the weight-gradient reduction's first pass: every producer's
+    partial rows read once (FP32) and the 32 row-split sums written (FP64).
+    Rows: one per ARM band, per synthesis-adjoint workgroup (64-pixel chunks,
+    syn_cpw each), per residual-adjoint workgroup (8x64 tiles, res_tpw each)
+    and per upsampling-adjoint tile (16x16, per channel; one per source on
+    the coarse levels whose output grid has at most 2,048 positions)."""
+    import numpy as np
+    from paper_2605_02726_amd import workloads as wl
+    spec = wl.param_spec(mc)
+    cnt = lambda pre: sum(int(np.prod(sh)) for nm, sh, _ in spec if nm.startswith(pre))
+    L = mc.L
+    gh = [H >> k for k in range(L)]
+    gw = [W >> k for k in range(L)]
+    bands = sum((H >> k) // 2 + (H >> k) % 2 for k in wl.grid_levels(mc))
+    jc = L
+    while jc > 1 and gh[jc - 2] * gw[jc - 2] <= 2048:
+        jc -= 1
+    ups_rows = sum(-(-gh[j] // 16) * -(-gw[j] // 16) * (L - j) if j < jc else L - j for j in range(1, L))
+    syn_rows = -(-(-(-H * W // 64)) // syn_cpw)
+    res_rows = -(-(-(-H // 8) * -(-W // 64)) // res_tpw)
+    rows = (bands * (cnt("arm.") + cnt("ifce.")) + ups_rows * 4 + syn_rows * cnt("syn.")
+            + res_rows * 84 * mc.n_res)
+    return 4 * rows + 8 * 32 * wl.n_params(mc)
+
+
+def hbm_bytes_per_step(mc, H, W, syn_cpw=12, res_tpw=1):
     """Algorithmic HBM bytes per launch-group of the HBM-bound kernels of one
     512x768 step (each array read or written once, FP32)."""
     L = mc.L
@@ -151,8 +177,9 @@ def hbm_bytes_per_step(mc, H, W):
         "ups_fwd": ups_fwd,                            # read T_j, write U_j (all levels)
         "ups_bwd": ups_bwd,                            # read dU_j and T_j, write dT_j (all levels)
         # latent join + Adam: read 3 rate planes, distortion grad, dq, theta, m, v and the
-        # IFCE parent gradients; write grad, theta, m, v
-        "join": 4 * n_lat * 12 + ifce,
+        # IFCE parent gradients; write grad, theta, m, v; in the same launch the first
+        # pass of the weight-gradient reduction
+        "join": 4 * n_lat * 12 + ifce + reduction_pass_bytes(mc, H, W, syn_cpw, res_tpw),
     }
 
 
@@ -256,7 +283,8 @@ def measure_batch(steps, warmup, precision="bf16", n=16):
     js = ms.value / max(cnt.value, 1) / 1e3
     res["join_adam"] = {"bytes_per_launch": jb, "avg_launch_ms": round(1e3 * js, 4),
                         "achieved_GBs": round(jb / js / 1e9, 1), "peak_GBs": PEAKS["hbm_GBs"],
-                        "frac": round(jb / js / 1e9 / PEAKS["hbm_GBs"], 4), "branches": "in order"}
+                        "frac": round(jb / js / 1e9 / PEAKS["hbm_GBs"], 4), "branches": "in order",
+                        "note": "with the first weight-gradient reduction pass (one launch)"}
     del encs
     return res
 
@@ -403,7 +431,8 @@ def main():
 
     hbm = None
     if not args.no_kernel_timing and not args.only_step:
-        bts = hbm_bytes_per_step(mc, H, W)
+        shp = shapes.get(head) or {}
+        bts = hbm_bytes_per_step(mc, H, W, shp.get("syn_chunks_per_wg", 12), shp.get("res_tiles_per_wg", 1))
         hbm = {}
         for name in ("ups_fwd", "ups_bwd", "join"):
             ms = measure_kernel(head, name, shape=shapes.get(head))
@@ -411,6 +440,7 @@ def main():
                          "achieved_GBs": round(bts[name] / (ms / 1e3) / 1e9, 1),
                          "peak_GBs": PEAKS["hbm_GBs"],
                          "frac": round(bts[name] / (ms / 1e3) / 1e9 / PEAKS["hbm_GBs"], 4)}
+        hbm["join"]["note"] = "latent join + Adam and the first weight-gradient reduction pass (one launch)"
     batched = measure_batch(args.batch_steps, 3) if args.batch_steps > 0 else None
     serving = measure_serving(args.serve_requests, args.serve_iters) if args.serve_requests > 0 else None
 

@@ -303,7 +303,8 @@ int cc_arm_band_plan(const cc_config* cfg, int H, int W, int nw, int* nbands, in
 /* Live kernel timing for measurement tools: HIP events are recorded on the
  * launch stream around every launch of one kernel class ("arm", "syn_bwd",
  * "res_bwd", "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which
- * also applies the latents' Adam update in an encode step; NULL or "" switches
+ * also applies the latents' Adam update in an encode step and shares its
+ * launch with the first pass of the weight-gradient reduction; NULL or "" switches
  * timing off; the upsampling and residual classes time all levels or layers of
  * one step as one span) by the calls that follow.  cc_timing_read waits for those events and returns the summed
  * duration (ms) and the number of timed launches, then resets the record.

@@ -979,18 +979,20 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
       RET(ups_backward(s, n, st));
     }
     RET(fk.join());
-    {
-      // latent gradients, with the latents' Adam update when updating
-      TimeScope ts(TK_JOIN, st);
-      RET(cc_launch_join(plan(s, n, [](const DevDesc& h) { return h.lat_ntile; }), st, nullptr,
-                         update ? 1 : 0));
-    }
-    // decoder-parameter gradients (with their Adam update) and, in one extra
-    // block per image, the loss totals
+    // latent gradients (with the latents' Adam update when updating) and the
+    // first pass of the decoder-parameter gradients in one launch, then the
+    // second pass (with their Adam update) and, in one extra block per image,
+    // the loss totals
     const bool soap = s[0]->optimizer == CC_OPT_SOAP;
-    const Launch w1 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, 64) * CC_WRED_SPLIT; });
+    const Launch lj = plan(s, n, [](const DevDesc& h) {
+      return h.lat_ntile + cdiv(h.n_par, 64) * CC_WRED_SPLIT;
+    });
     const Launch w2 = plan(s, n, [](const DevDesc& h) { return cdiv(h.n_par, CC_ELT_TILE) + 1; });
-    RET(cc_launch_wreduce(w1, w2, (update && !soap) ? 1 : 0, st));
+    {
+      TimeScope ts(TK_JOIN, st);
+      RET(cc_launch_join_wreduce1(lj, update ? 1 : 0, st));
+    }
+    RET(cc_launch_wreduce2(w2, (update && !soap) ? 1 : 0, st));
     if (update && soap) {
       // SOAP on the decoder parameters: one workgroup per parameter tensor
       SoapPack a;

@@ -135,6 +135,11 @@ int cc_launch_qtrain(const Launch& l, const StepPack& a, hipStream_t st);
 int cc_launch_arm(const Launch& l, const DevDesc& h, int bwd, int precision, hipStream_t st);
 int cc_launch_pool(const Launch& l, hipStream_t st);
 int cc_launch_join(const Launch& l, hipStream_t st, float* rate_only_out = nullptr, int adam = 0);
+// join + first reduction pass in one launch (lj: lat_ntile + the reduction's
+// blocks per image; the latents' Adam update when adam_latents); the second
+// pass (the parameters' Adam update when adam_params)
+int cc_launch_join_wreduce1(const Launch& lj, int adam_latents, hipStream_t st);
+int cc_launch_wreduce2(const Launch& l2, int adam_params, hipStream_t st);
 int cc_launch_poke(float* p, float v, hipStream_t st);
 int cc_launch_ups_fwd(const Launch& l, int j, hipStream_t st);
 int cc_launch_ups_bwd(const Launch& l, int j, hipStream_t st);

@@ -190,10 +190,8 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
 // context gradients of the positions that use this latent as a causal
 // neighbour (reversed offsets) and the IFCE gradients of finer grids; a
 // hyperlatent (grid >= L) feeds every IFCE and has no distortion term.
-__global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only_out, int adam) {
-  const int im = cc_find_img(L, blockIdx.x);
-  const CDesc* d = (const CDesc*)L.d[im];
-  const int i = (blockIdx.x - L.tile0[im]) * CC_ELT_TILE + threadIdx.x;
+__device__ __forceinline__ void join_tile(const CDesc* d, int tile, float* rate_only_out, int adam) {
+  const int i = tile * CC_ELT_TILE + threadIdx.x;
   if (i >= d->n_lat) return;
   const int k = grid_of(d, i);
   const int h = d->gh[k], w = d->gw[k], li = i - d->goff[k];
@@ -235,6 +233,11 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only
   if (adam && d->upd) adam_update(d, i, g);
 }
 
+__global__ __launch_bounds__(CC_ELT_TILE) void k_join(Launch L, float* rate_only_out, int adam) {
+  const int im = cc_find_img(L, blockIdx.x);
+  join_tile((const CDesc*)L.d[im], blockIdx.x - L.tile0[im], rate_only_out, adam);
+}
+
 __global__ void k_poke(float* p, float v) { *p = v; }
 
 __device__ __forceinline__ double block_sum_256(double v, double* sh) {
@@ -272,11 +275,7 @@ __global__ __launch_bounds__(256) void k_lreduce(Launch L) {
 
 // Weight-gradient reduction, pass 1: block (param block of 64, row split s)
 // sums its share of every producer's partial rows in FP64, fixed order.
-__global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
-  __shared__ double sh[4][64];
-  const int im = cc_find_img(L, blockIdx.x);
-  const CDesc* d = (const CDesc*)L.d[im];
-  const int b = blockIdx.x - L.tile0[im];
+__device__ __forceinline__ void wreduce1_block(const CDesc* d, int b, double (*sh)[64]) {
   const int pb = b / CC_WRED_SPLIT, s = b - pb * CC_WRED_SPLIT;
   const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
   const int p = pb * 64 + lane;
@@ -296,6 +295,26 @@ __global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
   __syncthreads();
   if (sub == 0 && p < d->n_par)
     d->wp2[(size_t)s * d->n_par + p] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+}
+
+__global__ __launch_bounds__(256) void k_wreduce1(Launch L) {
+  __shared__ double sh[4][64];
+  const int im = cc_find_img(L, blockIdx.x);
+  wreduce1_block((const CDesc*)L.d[im], blockIdx.x - L.tile0[im], sh);
+}
+
+// The latent join (with the latents' Adam update) and the first pass of the
+// weight-gradient reduction in one launch: per image, the join's tiles first,
+// then the reduction's blocks (the two read disjoint data).
+__global__ __launch_bounds__(256) void k_join_wreduce1(Launch L, int adam) {
+  __shared__ double sh[4][64];
+  const int im = cc_find_img(L, blockIdx.x);
+  const CDesc* d = (const CDesc*)L.d[im];
+  const int b = blockIdx.x - L.tile0[im];
+  if (b < d->lat_ntile)
+    join_tile(d, b, nullptr, adam);
+  else
+    wreduce1_block(d, b - d->lat_ntile, sh);
 }
 
 // Pass 2: gradient of decoder parameter p = sum of the row splits.
@@ -354,6 +373,14 @@ int cc_launch_poke(float* p, float v, hipStream_t st) {
 }
 int cc_launch_lreduce(const Launch& l, hipStream_t st) {
   hipLaunchKernelGGL(k_lreduce, dim3(l.n), dim3(256), 0, st, l);
+  return check_launch();
+}
+int cc_launch_join_wreduce1(const Launch& lj, int adam_latents, hipStream_t st) {
+  hipLaunchKernelGGL(k_join_wreduce1, dim3(lj.tile0[lj.n]), dim3(256), 0, st, lj, adam_latents);
+  return check_launch();
+}
+int cc_launch_wreduce2(const Launch& l2, int adam_params, hipStream_t st) {
+  hipLaunchKernelGGL(k_wreduce2, dim3(l2.tile0[l2.n]), dim3(CC_ELT_TILE), 0, st, l2, adam_params);
   return check_launch();
 }
 int cc_launch_wreduce(const Launch& l1, const Launch& l2, int adam, hipStream_t st) {
