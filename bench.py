@@ -38,12 +38,12 @@ PEAKS = {
 # calibration (FETCH x2.000, WRITE x1.000); the commands and the table are in
 # profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
 # until the counters are taken again.
-ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3609.9 + 1.0 * 18674.8) * 1024)
+ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3609.9 + 1.0 * 18673.3) * 1024)
 # Wave-level VALU instructions and MFMA-busy fraction per launch of the same
 # kernel (SQ_INSTS_VALU, MfmaUtil), from the counter pass in
 # profiles/mfma_valu_activity_bf16_512x768.txt; None when the kernel changes.
 ARM_FUSED_VALU_INSTS = 1.748e7
-ARM_FUSED_MFMA_UTIL = 0.0398
+ARM_FUSED_MFMA_UTIL = 0.0399
 
 
 def arm_flops_per_step(mc, H, W):
