@@ -138,3 +138,14 @@ def test_arm_band_packing(lib, mk, H, W):
     with pytest.raises(AssertionError):
         assert lib.lib().cc_arm_band_plan(C.byref(cfg), H, W, nb.value + 1, None, None,
                                           (C.c_int * (nb.value + 2))(), None) == 0
+
+
+def test_batch_sizes_outside_the_limit_are_rejected(lib):
+    """Empty and oversized batches fail on the host (no device call)."""
+    L = lib.lib()
+    p = (lib.cc_step_params * 40)()
+    states = (C.c_void_p * 40)()
+    for n in (0, -1, lib.CC_MAX_BATCH + 1):
+        assert L.cc_encode_step_batch(states, n, p, None, None) == lib.CC_EINVAL
+    # a batch whose states are not initialised
+    assert L.cc_encode_step_batch(states, 1, p, None, None) != lib.CC_OK
