@@ -19,8 +19,9 @@ from paper_2605_02726_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("name", ["plain", "hyper"])
-def test_short_encode_against_the_oracle(name):
+def test_short_encode_against_the_oracle(name, precision):
     from paper_2605_02726_amd.encoder import Encoder, schedule
     gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                                        "hyper_encode_128x192_300.json")))
@@ -28,7 +29,7 @@ def test_short_encode_against_the_oracle(name):
     H, W, seed, lam, n = 128, 192, 6, 1e-3, gold["n_iter"]
     enc = Encoder(mc, torch.from_numpy(wl.synth_image(H, W, seed)), lam, seed,
                   np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, seed),
-                  precision="fp32")
+                  precision=precision)
     for t in range(1, n + 1):
         enc.step(t, *schedule(t, n), sync=False)
     rd = enc.rd_eval()

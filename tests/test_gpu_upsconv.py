@@ -78,7 +78,8 @@ def test_conv_taps_follow_the_oracle_over_steps():
     assert np.allclose(got, ref, rtol=0, atol=1e-5)
 
 
-def test_short_encode_against_the_oracle():
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_short_encode_against_the_oracle(precision):
     """300 iterations of a 128x192 encode from identity taps against the FP64
     oracle's results (tests/golden/conv_encode_128x192_300.json), with the
     trajectory criterion of the hyperlatent encode: J within 1%, bits within
@@ -92,7 +93,7 @@ def test_short_encode_against_the_oracle():
     H, W, seed, lam, n = 128, 192, 6, 1e-3, gold["n_iter"]
     enc = Encoder(mc, torch.from_numpy(wl.synth_image(H, W, seed)), lam, seed,
                   np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, seed),
-                  precision="fp32")
+                  precision=precision)
     for t in range(1, n + 1):
         enc.step(t, *schedule(t, n), sync=False)
     rd = enc.rd_eval()
