@@ -602,7 +602,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   Lo.off_abl = take(sizeof(int) * (size_t)h.arm_nwg_fused);
   Lo.off_awb = take(sizeof(int) * (size_t)(h.arm_nwg_fused + 1));
   Lo.off_lpm = take(sizeof(double) * (size_t)h.pix_ntile);
-  Lo.off_scal = take(sizeof(double) * 4);
+  Lo.off_scal = take(sizeof(double) * 8);
   Lo.off_stab = take(sizeof(int) * Lo.soap_tab.size());
   Lo.off_sm = take(sizeof(float) * (size_t)h.n_par);
   Lo.off_sv = take(sizeof(float) * (size_t)h.n_par);
@@ -1141,6 +1141,7 @@ int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, doub
   if (e == hipSuccess) e = cp(h.m, zeros.data(), sizeof(float) * h.n_theta);
   if (e == hipSuccess) e = cp(h.v, zeros.data(), sizeof(float) * h.n_theta);
   if (e == hipSuccess) e = cp(h.grad, zeros.data(), sizeof(float) * h.n_theta);
+  if (e == hipSuccess) e = cp(h.scal, zeros.data(), sizeof(double) * 8);
   if (e == hipSuccess) e = cp(h.arm_gtab, s->lo.arm_gtab.data(), sizeof(unsigned) * s->lo.arm_gtab.size());
   if (e == hipSuccess) e = cp(h.syn_gtab, s->lo.syn_gtab.data(), sizeof(unsigned) * s->lo.syn_gtab.size());
   if (e == hipSuccess) e = cp(h.arm_ftab, s->lo.arm_ftab.data(), sizeof(unsigned) * s->lo.arm_ftab.size());

@@ -166,13 +166,14 @@ __global__ __launch_bounds__(64) void k_arm_plain(Launch Lc) {
       o1 += s1;
     }
 
-    const float lcl = fminf(fmaxf(o1, d->lmin), d->lmax);
+    // the clamp and the floor below let a NaN through (it then reaches the loss)
+    const float lcl = o1 != o1 ? o1 : fminf(fmaxf(o1, d->lmin), d->lmax);
     const bool lin = o1 >= d->lmin && o1 <= d->lmax;
     const float ib = expf(-lcl);
     const float yv = valid ? yg[li] : 0.0f;
     float bits, gd, gl;
     laplace_bits(yv - o0, ib, bits, gd, gl);
-    if (!(bits <= d->bits_max)) {
+    if (bits > d->bits_max) {
       bits = d->bits_max;
       gd = 0.0f;
       gl = 0.0f;

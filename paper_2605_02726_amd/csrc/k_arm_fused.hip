@@ -380,12 +380,13 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       const float mu = (o0 + p0) + (b30 + bs0);
       const float ls = (o1 + p1) + (b31 + bs1);
       // ---- rate (FP32)
-      const float lcl = fminf(fmaxf(ls, d->lmin), d->lmax);
+      // the clamp and the floor below let a NaN through (it then reaches the loss)
+      const float lcl = ls != ls ? ls : fminf(fmaxf(ls, d->lmin), d->lmax);
       const bool lin = ls >= d->lmin && ls <= d->lmax;
       const float yv = ywin[HALO + r][lc];
       float bits, gd, gl;
       laplace_bits(yv - mu, expf(-lcl), bits, gd, gl);
-      if (!(bits <= d->bits_max)) {
+      if (bits > d->bits_max) {
         bits = d->bits_max;
         gd = 0.0f;
         gl = 0.0f;

@@ -96,6 +96,15 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L, StepPack A) {
     dw->mode = a.mode;
     dw->upd = a.upd;
   }
+  if (b == 0) {
+    // A non-finite decoder parameter need not reach the loss (a ReLU maps a
+    // NaN pre-activation to 0), so the step checks them all here and the
+    // loss totals report the state as non-finite (scal[4] = 1).
+    int bad = 0;
+    for (int p = threadIdx.x; p < d->n_par; p += CC_ELT_TILE) bad |= !isfinite(d->theta[d->n_lat + p]);
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) d->scal[4] = bad ? 1.0 : 0.0;
+  }
   const int i = b * CC_ELT_TILE + threadIdx.x;
   if (i >= d->n_lat) return;
   const float y = d->theta[i];
@@ -250,7 +259,9 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh) {
   return sh[0];
 }
 
-// FP64 totals of one image in a fixed order: scal = (loss, bits, mse, finite).
+// FP64 totals of one image in a fixed order: scal = (loss, bits, mse, finite);
+// finite also needs every decoder parameter finite (scal[4], set by the
+// quantiser kernel of the same step).
 __device__ void loss_totals(const CDesc* d, double* sh) {
   double b = 0.0, m = 0.0;
   for (int r = threadIdx.x; r < d->arm_nwg; r += 256) b += d->lp_bits[r];
@@ -264,7 +275,7 @@ __device__ void loss_totals(const CDesc* d, double* sh) {
     d->scal[0] = loss;
     d->scal[1] = bits;
     d->scal[2] = mse;
-    d->scal[3] = isfinite(loss) ? 1.0 : 0.0;
+    d->scal[3] = (isfinite(loss) && d->scal[4] == 0.0) ? 1.0 : 0.0;
   }
 }
 

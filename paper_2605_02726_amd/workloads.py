@@ -80,6 +80,16 @@ def config_hop() -> ModelConfig:
                        syn_hidden=[40], syn_stab=1, n_res=2)
 
 
+def config_hop_s18() -> ModelConfig:
+    """The other reading of the 512x768 workload's ARM: 18 spatial
+    neighbours + F=6 inter-feature context, so that the context is 24 wide
+    (ARM 24->24->24->2 with stabilizer); the rest as config_hop (2,067
+    decoder parameters)."""
+    c = config_hop()
+    c.n_spatial = 18
+    return c
+
+
 # Table II presets for images below 10^6 pixels (7 latent grids, hyperlatent
 # grids 1/16 .. 1/64): inter-feature context F on the 1/1, 1/2, 1/4 grids,
 # spatial context s, two ARM hidden layers of the given width, one 1x1

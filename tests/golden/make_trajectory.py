@@ -2,6 +2,7 @@
 
     python tests/golden/make_trajectory.py [n_iter]
     python tests/golden/make_trajectory.py n_iter --perturb REL SEED
+    python tests/golden/make_trajectory.py n_iter --fp32-storage
 
 Calls only the oracle and the seeded input generator: one 512x768 image
 (seed 2, 1/f field + 32 rectangles), the 2,223-parameter decoder, latents 0,
@@ -14,6 +15,10 @@ With --perturb, every gradient element is multiplied by (1 + REL xi) before
 Adam, xi standard normal from PCG64(SEED, t): the same trajectory under
 gradient errors of the size FP32 arithmetic makes, which measures how far
 two correct implementations can drift apart after n_iter iterations.
+
+With --fp32-storage, the latents, decoder parameters and both Adam moments
+are rounded to float32 after every update (the arithmetic stays float64):
+the storage precision of a GPU state, on its own.
 """
 import json
 import os
@@ -36,6 +41,7 @@ def main():
     if "--perturb" in sys.argv:
         i = sys.argv.index("--perturb")
         rel, pseed = float(sys.argv[i + 1]), int(sys.argv[i + 2])
+    fp32_storage = "--fp32-storage" in sys.argv
     torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     mc = wl.config_hop()
     H, W, seed, lam = 512, 768, 2, 1e-3
@@ -55,6 +61,9 @@ def main():
             st.theta, st.m, st.v = R.adam(st.theta, g * (1.0 + rel * xi), st.m, st.v, t, lr)
             st.t = t
             steps.append((loss, bits, mse))
+        if fp32_storage:
+            st.theta, st.m, st.v = (np.asarray(a, np.float32).astype(np.float64)
+                                    for a in (st.theta, st.m, st.v))
         if t in checkpoints:
             rd[str(t)] = st.rd_eval()
             print(f"t={t} loss {steps[-1][0]:.6f} rd {rd[str(t)]} ({time.time() - t0:.0f} s)",
@@ -66,6 +75,9 @@ def main():
     if rel != 0.0:
         out["perturbation"] = {"relative": rel, "seed": pseed}
         name = f"trajectory_512x768_{n_iter}_perturbed_{pseed}.json"
+    if fp32_storage:
+        out["storage"] = "float32 theta, m, v after every update"
+        name = name.replace(".json", "_fp32storage.json")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     with open(path, "w") as f:
         json.dump(out, f)

@@ -41,6 +41,9 @@ CASES = {
     "tiny_64x32_random": (wl.config_tiny, 64, 32, 13, True),
     "hop_512x768_init": (wl.config_hop, 512, 768, 2, False),
     "hop_320x1088_random": (wl.config_hop, 320, 1088, 14, True),   # ragged against every tile
+    # the 18 + 6 reading of the workload's ARM context (24-wide context)
+    "hop_s18_128x192_random": (wl.config_hop_s18, 128, 192, 23, True),
+    "hop_s18_512x768_init": (wl.config_hop_s18, 512, 768, 2, False),
     # hyperlatent grids (1/16 .. 1/64) feeding the IFCEs
     "hop_hyper_128x192_random": (wl.config_hop_hyper, 128, 192, 19, True),
     "hop_hyper_512x768_init": (wl.config_hop_hyper, 512, 768, 2, False),
