@@ -167,6 +167,22 @@ int cc_eval_loss(cc_state* s, const cc_step_params* p, double* out3, void* strea
 /* Rate and distortion with hard quantisation, no gradient.  Synchronises. */
 int cc_rd_eval(cc_state* s, cc_rd_result* out, void* stream);
 
+/* cc_rd_eval for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels in the same order, so `out` is bit for bit cc_rd_eval's,
+ * but every buffer the evaluation writes (a copy of the state's descriptor,
+ * quantised latents, upsampled planes, synthesis activations, FP64 partial
+ * sums) lives in a static device array of 64 MiB that the library holds on
+ * each device it runs on until the process ends; the state slab is only read.
+ * The array covers images up to about 0.75 megapixel with the workload's
+ * decoder (a 512x768 state uses 34 MiB); a larger state returns CC_ENOMEM
+ * before anything is queued.  Allocates nothing (no hipMalloc, no library
+ * allocation); synchronises `stream`.  Every call on a device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (two streams or threads at once) race and must be serialised by
+ * the caller. */
+int cc_rd_eval_noalloc(cc_state* s, cc_rd_result* out, void* stream);
+
 /* Quantisation and transmission rate of the decoder parameters (Section
  * IV-E).  Submodules a = 0 ARM, 1 synthesis (with the residual layers),
  * 2 upsampling, 3 IFCE; w = 0 weights, 1 biases.  For every submodule in

@@ -73,6 +73,7 @@ _PROTOS = [
                                        C.c_void_p, C.c_void_p]),
     ("cc_eval_loss", C.c_int, [C.c_void_p, C.POINTER(cc_step_params), C.c_void_p, C.c_void_p]),
     ("cc_rd_eval", C.c_int, [C.c_void_p, C.POINTER(cc_rd_result), C.c_void_p]),
+    ("cc_rd_eval_noalloc", C.c_int, [C.c_void_p, C.POINTER(cc_rd_result), C.c_void_p]),
     ("cc_nn_quantize", C.c_int, [C.c_void_p, C.POINTER(cc_nnq_result), C.c_void_p]),
     ("cc_decode", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("cc_get_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -16,6 +16,10 @@
 
 #include "cc_internal.h"
 
+// Static scratch of cc_rd_eval_noalloc (one copy per device, held until the
+// process ends; host code reaches it only through hipGetSymbolAddress).
+static __device__ __align__(256) char scratch[CC_NOALLOC_SCRATCH_BYTES];
+
 int cc_arm_shape_supported(int S, int F, int H1, int H2);
 int cc_syn_shape_supported(int nh, int w1, int w2);
 int cc_launch_arm_plain(const Launch& l, const DevDesc& h, int bwd, hipStream_t st);
@@ -1034,6 +1038,69 @@ int check_state(const cc_state* s) {
   return CC_OK;
 }
 
+// ------------------------------------------------ no-allocation evaluation --
+// cc_rd_eval_noalloc keeps every buffer its kernels write (a relocated copy
+// of the descriptor, quantised latents, upsampled planes, synthesis
+// activations, FP64 partial sums and totals) in this array instead of the
+// state slab.  Host code never uses the symbol's name as an address: each
+// device's copy is looked up once with hipGetSymbolAddress (at the first
+// cc_init_state on that device, with the device current) and only that
+// pointer is passed to kernels and copies.
+constexpr size_t kNoallocBytes = CC_NOALLOC_SCRATCH_BYTES;
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxSideDev] = {};
+
+// The calling thread's current device's copy of `scratch` (looked up on the
+// first call per device).
+int scratch_for_device(int dev, char** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxSideDev) return fail(CC_EDEVICE, "device %d outside the supported range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != dev)
+      return fail(CC_EDEVICE, "the state's device %d is not current", dev);
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();   // not left for the next launch check to report
+      return fail(CC_EDEVICE, "scratch symbol lookup failed: %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CC_OK;
+}
+
+// Descriptor of state h with every buffer an evaluation writes relocated into
+// the scratch array at base; returns the bytes used (0 if they do not fit).
+size_t relocate_eval(DevDesc& h, char* base) {
+  size_t o = 0;
+  auto take = [&](size_t n) {
+    const size_t r = o;
+    o = al256(o + n);
+    return base + r;
+  };
+  const size_t npix = (size_t)h.H * h.W;
+  size_t un = 0, vn = 0;
+  for (int j = 1; j < h.L; ++j) {
+    un += (size_t)(h.L - j) * h.gh[j - 1] * h.gw[j - 1];
+    if (h.ups_conv) vn += (size_t)(h.L - j) * h.gh[j] * h.gw[j];
+  }
+  take(sizeof(DevDesc));
+  h.yhat = (float*)take(sizeof(float) * (size_t)h.n_lat);
+  h.dq = (float*)take(sizeof(float) * (size_t)h.n_lat);
+  h.U = (float*)take(sizeof(float) * std::max<size_t>(un, 1));
+  h.V = (float*)take(sizeof(float) * std::max<size_t>(vn, 1));
+  h.X = (float*)take(sizeof(float) * (size_t)(h.n_res + 1) * 3 * npix);
+  h.dXa = (float*)take(sizeof(float) * 3 * npix);   // the MSE epilogue's gradient
+  h.lp_bits = (double*)take(sizeof(double) * (size_t)std::max(std::max(h.arm_nwg_plain, h.arm_nwg_fused), 1));
+  h.lp_mse = (double*)take(sizeof(double) * (size_t)std::max(h.pix_ntile, 1));
+  h.scal = (double*)take(sizeof(double) * 8);
+  return o <= kNoallocBytes ? o : 0;
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -1115,6 +1182,11 @@ int cc_init_state(const cc_config* cfg, int H, int W, const float* img_dev, doub
   s->precision = cfg->precision;
   s->ddev = (DevDesc*)(s->base + s->lo.off_desc);
   if (hipGetDevice(&s->device) != hipSuccess) s->device = -1;
+  {
+    // set-up of the no-allocation evaluation's array on this device (once)
+    char* sp = nullptr;
+    if (s->device >= 0) (void)scratch_for_device(s->device, &sp);
+  }
   set_pointers(s->lo, s->base);
   DevDesc& h = s->lo.h;
   h.lambda = lambda;
@@ -1214,6 +1286,41 @@ int cc_rd_eval(cc_state* s, cc_rd_result* out, void* stream) {
   HIPCHK(hipStreamSynchronize(st));
   if (out) {
     const double hw = (double)s->lo.h.H * s->lo.h.W;
+    out->loss = sc[0];
+    out->bits = sc[1];
+    out->mse = sc[2];
+    out->bpp = sc[1] / hw;
+    out->psnr = sc[2] > 0 ? 10.0 * log10(1.0 / sc[2]) : INFINITY;
+  }
+  return CC_OK;
+}
+
+int cc_rd_eval_noalloc(cc_state* s, cc_rd_result* out, void* stream) {
+  if (!s || !s->ddev) return fail(CC_ESTATE, "state not initialised");
+  char* base = nullptr;
+  RET(scratch_for_device(s->device, &base));
+  DevDesc h = s->lo.h;
+  const size_t used = relocate_eval(h, base);
+  if (used == 0)
+    return fail(CC_ENOMEM, "evaluation of a %dx%d state needs more than the %zu bytes of static scratch",
+                s->lo.h.H, s->lo.h.W, kNoallocBytes);
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(base, &h, sizeof(DevDesc), hipMemcpyHostToDevice, st));
+  cc_step_params p{};
+  p.t = 1;
+  p.quant_mode = CC_HARD;
+  p.temperature = 1.0f;
+  // the same launches as cc_rd_eval, reading the relocated descriptor
+  DevDesc* const own = s->ddev;
+  s->ddev = (DevDesc*)base;
+  const int rc = run_step(&s, 1, &p, st, false, false);
+  s->ddev = own;
+  RET(rc);
+  double sc[4];
+  HIPCHK(hipMemcpyAsync(sc, h.scal, sizeof sc, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));   // also keeps h alive until its copy is done
+  if (out) {
+    const double hw = (double)h.H * h.W;
     out->loss = sc[0];
     out->bits = sc[1];
     out->mse = sc[2];

@@ -12,6 +12,7 @@
 #define CC_MAX_NIN 10 // inputs of one IFCE (coarser latent grids + hyperlatent grids)
 #define CC_MAX_S 32
 #define CC_MAX_PROD 24
+#define CC_NOALLOC_SCRATCH_BYTES (64u << 20)  // static scratch of cc_rd_eval_noalloc, per device
 
 // One producer of weight-gradient partial rows (a kernel whose workgroups
 // each write the sum of their positions' contributions to a parameter range).
