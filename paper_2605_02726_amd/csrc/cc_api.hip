@@ -397,7 +397,12 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
     }
   }
   {
-    // fused ARM: parameter -> (grid requirement, accumulator, row, column)
+    // fused ARM: parameter -> (grid requirement, accumulator, row, column) of
+    // its weight-gradient accumulators: 0 = dH1 C^T (stabilizer rows H1,
+    // H1 + 1; bias column CTX), 1 = dH2 H1^T (bias column H1), 2 = rows H1,
+    // H1 + 1 (d mu, d l) against H2^T (bias column H2), 3 = the IFCE rows
+    // S + f of the context gradient against the IFCE inputs (bias column
+    // CC_MAX_NIN), taken only from the bands of the IFCE's own grid
     auto ent = [](int k, int a, int row, int col) {
       return ((unsigned)(k & 0xFF) << 16) | ((unsigned)a << 10) | ((unsigned)row << 5) | (unsigned)col;
     };
@@ -413,25 +418,18 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
       t[h.p_ab[1] + u] = ent(0xFF, 1, u, h.H1);
     }
     for (int a = 0; a < 2; ++a) {
-      for (int q2 = 0; q2 < h.H2; ++q2) t[h.p_aw[2] + a * h.H2 + q2] = ent(0xFF, 2, a, q2);
-      t[h.p_ab[2] + a] = ent(0xFF, 2, a, h.H2);
+      for (int q2 = 0; q2 < h.H2; ++q2) t[h.p_aw[2] + a * h.H2 + q2] = ent(0xFF, 2, h.H1 + a, q2);
+      t[h.p_ab[2] + a] = ent(0xFF, 2, h.H1 + a, h.H2);
       if (h.arm_stab) {
         for (int q2 = 0; q2 < CTX; ++q2) t[h.p_asw + a * CTX + q2] = ent(0xFF, 0, h.H1 + a, q2);
         t[h.p_asb + a] = ent(0xFF, 0, h.H1 + a, CTX);
       }
     }
-    // IFCE weights: inputs q < Q3 pair the context-gradient rows 2 + f of
-    // the output tile with the input columns H2 + 1 + q of the last hidden
-    // tile; the rest use the spare rows H2 + f and columns H1 + 1 + q - Q3
-    // of the second layer's tiles
-    const int Q3 = 32 - h.H2 - 1;
     for (int k = 0; k < h.G; ++k) {
       const int nin = h.nin[k];
       for (int f = 0; f < h.F; ++f) {
-        for (int q2 = 0; q2 < nin; ++q2)
-          t[h.p_iw[k] + f * nin + q2] = q2 < Q3 ? ent(k, 2, 2 + f, h.H2 + 1 + q2)
-                                                : ent(k, 1, h.H2 + f, h.H1 + 1 + q2 - Q3);
-        t[h.p_ib[k] + f] = ent(k, 2, 2 + f, h.H2);
+        for (int q2 = 0; q2 < nin; ++q2) t[h.p_iw[k] + f * nin + q2] = ent(k, 3, h.S + f, q2);
+        t[h.p_ib[k] + f] = ent(k, 3, h.S + f, CC_MAX_NIN);
       }
     }
   }

@@ -25,7 +25,7 @@ constexpr float INV_LN2 = 1.4426950408889634f;
 // the derivatives d bits / d (yhat - mu) and b * d bits / d b, in FP32 with
 // expm1 forms that avoid cancellation:
 //   |d| >= 1/2:  bits = (|d| - 1/2) / (b ln 2) - log2(-expm1(-1/b) / 2)
-//   |d| <  1/2:  p = -(expm1(-(1/2 + d)/b) + expm1(-(1/2 - d)/b)) / 2
+//   |d| <  1/2:  p = 1 - (exp(-(1/2 + d)/b) + exp(-(1/2 - d)/b)) / 2
 __device__ __forceinline__ void laplace_bits(float dd, float ib, float& bits, float& gd,
                                              float& gl) {
   const float ad = fabsf(dd);
@@ -35,13 +35,20 @@ __device__ __forceinline__ void laplace_bits(float dd, float ib, float& bits, fl
     gd = copysignf(ib * INV_LN2, dd);
     gl = (ib / expm1f(ib) - a * ib) * INV_LN2;
   } else {
+    // with E1 = exp(-x1), E2 = exp(-x2): p = 1 - (E1 + E2) / 2, and the
+    // derivatives need E1 - E2 and E1 x1 + E2 x2; written with E's rather
+    // than expm1(-x) = E - 1, whose low bits (where E is small, at small
+    // scales b) FP32 cannot hold next to the -1
     const float x1 = (0.5f + dd) * ib, x2 = (0.5f - dd) * ib;
-    const float e1 = expm1f(-x1), e2 = expm1f(-x2);
-    const float p = -0.5f * (e1 + e2);
-    bits = -log2f(p);
+    const float E1 = expf(-x1), E2 = expf(-x2);
+    const float h = 0.5f * (E1 + E2);
+    const float p = 1.0f - h;
+    bits = -log1pf(-h) * INV_LN2;
     const float q = INV_LN2 / p;
-    gd = -0.5f * ib * (e1 - e2) * q;
-    gl = 0.5f * ((e1 + 1.0f) * x1 + (e2 + 1.0f) * x2) * q;
+    // E1 - E2 = E2 expm1(x2 - x1) (dd >= 0) or -E1 expm1(x1 - x2) (dd < 0)
+    const float dE = dd >= 0.0f ? E2 * expm1f(-2.0f * dd * ib) : -E1 * expm1f(2.0f * dd * ib);
+    gd = -0.5f * ib * dE * q;
+    gl = 0.5f * (E1 * x1 + E2 * x2) * q;
   }
 }
 

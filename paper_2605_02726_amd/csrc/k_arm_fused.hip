@@ -7,8 +7,12 @@
 //   backward  dH1 = W2^T dH2', dC = W1^T dH1'
 //   weights   dW1 = dH1' C^T, dW2 = dH2' H1^T, dW3/dWs/dW_ifce likewise
 // with latent positions on the N axis: 32 positions per MFMA, operands in
-// BF16, accumulation in FP32.  The output layer (2 units), the stabilizer,
-// the rate and its derivatives run in FP32 on the vector ALUs.
+// split BF16 (hi + lo), accumulation in FP32.  The output layer (2 units),
+// the stabilizer, the rate and its derivatives run in FP32 on the vector
+// ALUs.  The weight gradients need the positions on the K axis instead: each
+// operand is transposed through the matrix cores (a product with a constant
+// 0/1 permutation matrix, exact in FP32), so no activation passes through
+// LDS, and the weight-gradient products are split BF16 as well.
 //
 // Work: one workgroup (4 wavefronts) per band of 2 rows of one grid, swept in
 // segments of 128 columns; wavefront w owns columns [32 w, 32 w + 32) of the
@@ -89,48 +93,64 @@ __device__ __forceinline__ void laplace_bits(float dd, float ib, float& bits, fl
     gd = copysignf(ib * INV_LN2, dd);
     gl = (ib / expm1f(ib) - a * ib) * INV_LN2;
   } else {
+    // with E1 = exp(-x1), E2 = exp(-x2): p = 1 - (E1 + E2) / 2, and the
+    // derivatives need E1 - E2 and E1 x1 + E2 x2; written with E's rather
+    // than expm1(-x) = E - 1, whose low bits (where E is small, at small
+    // scales b) FP32 cannot hold next to the -1
     const float x1 = (0.5f + dd) * ib, x2 = (0.5f - dd) * ib;
-    const float e1 = expm1f(-x1), e2 = expm1f(-x2);
-    const float p = -0.5f * (e1 + e2);
-    bits = -log2f(p);
+    const float E1 = expf(-x1), E2 = expf(-x2);
+    const float h = 0.5f * (E1 + E2);
+    const float p = 1.0f - h;
+    bits = -log1pf(-h) * INV_LN2;
     const float q = INV_LN2 / p;
-    gd = -0.5f * ib * (e1 - e2) * q;
-    gl = 0.5f * ((e1 + 1.0f) * x1 + (e2 + 1.0f) * x2) * q;
+    // E1 - E2 = E2 expm1(x2 - x1) (dd >= 0) or -E1 expm1(x1 - x2) (dd < 0)
+    const float dE = dd >= 0.0f ? E2 * expm1f(-2.0f * dd * ib) : -E1 * expm1f(2.0f * dd * ib);
+    gd = -0.5f * ib * dE * q;
+    gl = 0.5f * (E1 * x1 + E2 * x2) * q;
   }
 }
 
-// Transposing tile: values written at [row][col], operands read as 8
-// consecutive columns of one row.
-struct Tile {
-  __bf16 v[32][32];
-};
-
-// acc += G * C^T over the 32 positions of a chunk: A operand = 8
-// consecutive positions of row n of G, B operand = the same of row n of C.
-__device__ __forceinline__ f32x16 mfma_tiles(const Tile& G, const Tile& C, int n, int hh,
-                                             f32x16 acc) {
+// acc += A * B over 32 positions on K (two K-steps), split BF16:
+// A_lo B_hi + A_hi B_lo + A_hi B_hi.
+__device__ __forceinline__ f32x16 mma_split(const bf16x8* ah, const bf16x8* al, const bf16x8* bh,
+                                            const bf16x8* bl, f32x16 acc) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    bf16x8 a, b;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      a[i] = G.v[n][16 * s + 8 * hh + i];
-      b[i] = C.v[n][16 * s + 8 * hh + i];
-    }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-  }
+  for (int s = 0; s < 2; ++s) acc = mfma3(ah[s], al[s], bh[s], bl[s], acc);
   return acc;
 }
 
+// Transpose of a 32 x 32 block held as a B operand (lane = position, K index
+// 16 s + 8 hh + i <-> feature) into the layout of an MFMA output with the
+// positions as rows (lane = feature, register i <-> position mrow(i, hh)):
+// D = X^T P with P the 0/1 matrix of the K index -> feature map, which an
+// FP32 accumulation reproduces exactly.  Registers 8 s .. 8 s + 7 of the
+// result, as BF16, are then an A or B operand with the positions on K.
+__device__ __forceinline__ void transpose2(const bf16x8* x, const bf16x8* p, bf16x8* out) {
+  f32x16 d = {};
+  d = mfma(x[0], p[0], d);
+  d = mfma(x[1], p[1], d);
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[s][i] = (__bf16)d[8 * s + i];
+}
+
+// Lanes of column n of a transposed operand: all ones (a bias column), or
+// zero.
+__device__ __forceinline__ void set_column(bf16x8* hi, bf16x8* lo, float v) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      hi[s][i] = (__bf16)v;
+      lo[s][i] = (__bf16)0.0f;
+    }
+}
+
 template <int S, int F, int H1, int H2>
-__global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
+__global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
   constexpr int CTX = S + F;
-  static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 <= 32, "shape");
-  // IFCE inputs q < Q3 go to the columns H2 + 1 + q of the last hidden
-  // tile, the others to the spare columns H1 + 1 + q - Q3 of the second
-  // layer's tile, paired with the context-gradient rows H2 + f there (the
-  // host checks that they fit)
-  constexpr int Q3 = 32 - H2 - 1;
+  static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 <= 32 && CC_MAX_NIN + 1 <= 32, "shape");
   // The linear stabilizer rides in the first layer's spare output rows H1,
   // H1 + 1 (and its backward in the same columns of the transposed layer):
   // register IS of half HS holds row H1, register IS + 1 row H1 + 1.
@@ -143,13 +163,11 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   // the next segment
   __shared__ float pacc[NW][HALO + TH][PW];
   __shared__ float cin[HALO + TH][2 * HALO], cout[HALO + TH][2 * HALO];
-  // per-wave transposing tiles; the end-of-kernel weight-gradient sum reuses
-  // the same storage
-  __shared__ __attribute__((aligned(16))) char tiles_raw[2 * 3 * NW * sizeof(Tile)];
-  Tile(*tg)[NW] = reinterpret_cast<Tile(*)[NW]>(tiles_raw);
-  Tile(*tc)[NW] = reinterpret_cast<Tile(*)[NW]>(tiles_raw + 3 * NW * sizeof(Tile));
-  float(*wsum)[32][33] = reinterpret_cast<float(*)[32][33]>(tiles_raw);
-  static_assert(3 * 32 * 33 * sizeof(float) <= 2 * 3 * NW * sizeof(Tile), "wsum alias");
+  // end-of-band weight-gradient sums of the four accumulators (the weights
+  // are staged through the same storage at the start)
+  __shared__ float wsum_raw[4 * 32 * 33];
+  float(*wsum)[32][33] = reinterpret_cast<float(*)[32][33]>(wsum_raw);
+  static_assert(H1 * CTX + H2 * H1 <= 4 * 32 * 33, "weight staging");
   __shared__ float pwin[CC_MAX_NIN][SW / 2 + 1];   // IFCE inputs of the segment
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
   __shared__ float iw[8][CC_MAX_NIN], ib[8];  // IFCE weights [feature][input] (zero padded), biases
@@ -179,7 +197,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   // operand (matrix mat, step s) of lane l is wop[mat][s][l] (hi) and
   // wopl[mat][s][l] (lo).  W1 and W2 are first staged in FP32 through the
   // (not yet used) tile storage; wavefront mat then builds matrix mat.
-  float* w1s = reinterpret_cast<float*>(tiles_raw);
+  float* w1s = wsum_raw;
   float* w2s = w1s + H1 * CTX;
   for (int i = tid; i < H1 * CTX + H2 * H1; i += NW * 64)
     w1s[i] = i < H1 * CTX ? P[d->p_aw[0] + i] : P[d->p_aw[1] + i - H1 * CTX];
@@ -212,6 +230,18 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       wopl[mat][s2][lane] = lo;
     }
   }
+  // 0/1 operands of the transposes: K index 16 s + 8 hh + i -> feature n
+  // (the hidden-unit registers carry unit kunit(k); the context and the IFCE
+  // inputs carry slot k)
+  bf16x8 pu[2], pc[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int kk = 16 * s2 + 8 * hh + i;
+      pu[s2][i] = (__bf16)(kunit(kk) == n ? 1.0f : 0.0f);
+      pc[s2][i] = (__bf16)(kk == n ? 1.0f : 0.0f);
+    }
   const float b30 = P[d->p_ab[2]], b31 = P[d->p_ab[2] + 1];
   const float bs0 = stab ? P[d->p_asb] : 0.0f, bs1 = stab ? P[d->p_asb + 1] : 0.0f;
   // this workgroup's bands (band index: grid 0's bands first, then grid
@@ -233,7 +263,6 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   const int y0 = band * TH;
   const bool has_ifce = F > 0 && k < d->G;
   const int nin = has_ifce ? d->nin[k] : 0;
-  const bool ifce_extra = nin > Q3;   // some inputs use the second layer's tiles
   const float* yg = d->yhat + d->goff[k];
   if (tid < 8 * CC_MAX_NIN) {
     const int f = tid / CC_MAX_NIN, q = tid - f * CC_MAX_NIN;
@@ -245,7 +274,13 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
 #pragma unroll
   for (int q = 0; q < CC_MAX_NIN; ++q) shq[q] = q < nin ? d->ish[k][q] : 1;
 
-  f32x16 acc1 = {}, acc2 = {}, acc3 = {};
+  // weight-gradient accumulators (rows x columns, positions summed):
+  // acc1 = dH1 C^T (+ stabilizer rows H1, H1 + 1; bias column CTX),
+  // acc2 = dH2 H1^T (bias column H1), acc3 = the same dH1 rows H1, H1 + 1
+  // (d mu, d l) against H2^T: the output layer (bias column H2),
+  // acc4 = dC (IFCE slots S + f) against the IFCE inputs (bias column
+  // CC_MAX_NIN)
+  f32x16 acc1 = {}, acc2 = {}, acc3 = {}, acc4 = {};
   double bsum = 0.0;
   for (int i = tid; i < NW * (HALO + TH) * PW; i += NW * 64) (&pacc[0][0][0])[i] = 0.0f;
   if (tid < (HALO + TH) * 2 * HALO) (&cin[0][0])[tid] = 0.0f;
@@ -288,16 +323,11 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
     }
     __syncthreads();
 
+#pragma unroll 1
     for (int r = 0; r < TH; ++r) {
       const int y = y0 + r, x = x0 + 32 * wave + n;
       const bool valid = y < h && x < w;
       const int lc = HALO + 32 * wave + n;       // LDS column of this position
-      Tile& G1 = tg[0][wave];
-      Tile& G2 = tg[1][wave];
-      Tile& G3 = tg[2][wave];
-      Tile& C1 = tc[0][wave];
-      Tile& C2 = tc[1][wave];
-      Tile& C3 = tc[2][wave];
       // ---- context (FP32) in operand order: slot kk = 16 s + 8 hh + i
       float r_in[CC_MAX_NIN];
 #pragma unroll
@@ -326,14 +356,6 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       split8(cf[0], bc[0], bcl[0]);
       split8(cf[1], bc[1], bcl[1]);
       const bool do_bwd = bwd > 0;
-      if (do_bwd) {
-        // weight-gradient columns known after the context: [context | 1]
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int i = 0; i < 8; ++i) C1.v[16 * s + 8 * hh + i][n] = bc[s][i];
-        if (hh == 0) C1.v[CTX][n] = (__bf16)1.0f;
-      }
       // ---- layer 1 (with the stabilizer in rows H1, H1 + 1) and 2
       f32x16 z = {};
       f32x16 D = mfma3(wop[0][0][lane], wopl[0][0][lane], bc[0], bcl[0], z);
@@ -351,30 +373,21 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
         split8(hv, bh[0], bhl[0]);
         split8(hv + 8, bh[1], bhl[1]);
       }
-      if (do_bwd) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) C2.v[mrow(i, hh)][n] = bh[i >> 3][i & 7];
-        if (hh == 0) C2.v[H1][n] = (__bf16)1.0f;
-      }
       D = mfma3(wop[1][0][lane], wopl[1][0][lane], bh[0], bhl[0], z);
       D = mfma3(wop[1][1][lane], wopl[1][1][lane], bh[1], bhl[1], D);
+      bf16x8 vh[2], vl[2];   // H2 (split, for the output layer's weight gradient)
+      {
+        float v2[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const float v = fmaxf(D[i] + vec[1][mrow(i, hh)], 0.0f);
-        m2 |= (v > 0.0f ? 1u : 0u) << i;
-        o0 += vec[2][mrow(i, hh)] * v;
-        o1 += vec[3][mrow(i, hh)] * v;
-        if (do_bwd) C3.v[mrow(i, hh)][n] = (__bf16)v;
-      }
-      if (do_bwd && hh == 0) {
-        C3.v[H2][n] = (__bf16)1.0f;
-#pragma unroll
-        for (int q = 0; q < CC_MAX_NIN; ++q) {
-          if (q < Q3)
-            C3.v[H2 + 1 + q][n] = (__bf16)r_in[q];
-          else if (ifce_extra && H1 + 1 + q - Q3 < 32)
-            C2.v[H1 + 1 + q - Q3][n] = (__bf16)r_in[q];
+        for (int i = 0; i < 16; ++i) {
+          const float v = fmaxf(D[i] + vec[1][mrow(i, hh)], 0.0f);
+          m2 |= (v > 0.0f ? 1u : 0u) << i;
+          o0 += vec[2][mrow(i, hh)] * v;
+          o1 += vec[3][mrow(i, hh)] * v;
+          v2[i] = v;
         }
+        split8(v2, vh[0], vl[0]);
+        split8(v2 + 8, vh[1], vl[1]);
       }
       const float p0 = __shfl_xor(o0, 32), p1 = __shfl_xor(o1, 32);
       const float mu = (o0 + p0) + (b30 + bs0);
@@ -402,63 +415,73 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
 
       // ---- backward
       const float dmu = -gd * rs, dl = gl * rs;
-      bf16x8 bd[2], bdl[2];
+      bf16x8 b2[2], b2l[2];   // dH2 (B operand, split)
       {
         float gv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i)
           gv[i] = ((m2 >> i) & 1u) ? vec[2][mrow(i, hh)] * dmu + vec[3][mrow(i, hh)] * dl : 0.0f;
-        split8(gv, bd[0], bdl[0]);
-        split8(gv + 8, bd[1], bdl[1]);
+        split8(gv, b2[0], b2l[0]);
+        split8(gv + 8, b2[1], b2l[1]);
       }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) G2.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
-      D = mfma3(wop[2][0][lane], wopl[2][0][lane], bd[0], bdl[0], z);
-      D = mfma3(wop[2][1][lane], wopl[2][1][lane], bd[1], bdl[1], D);
+      D = mfma3(wop[2][0][lane], wopl[2][0][lane], b2[0], b2l[0], z);
+      D = mfma3(wop[2][1][lane], wopl[2][1][lane], b2[1], b2l[1], D);
+      bf16x8 b1[2], b1l[2];   // dH1 with (d mu, d l) in the stabilizer rows
       {
         float gv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) gv[i] = ((m1 >> i) & 1u) ? D[i] : 0.0f;
         // (d mu, d l) enter at the stabilizer rows: the transposed first layer
-        // then adds the stabilizer's context gradient, and the weight-gradient
-        // tile gets its rows H1, H1 + 1
-        gv[IS] = hh == HS ? dmu : 0.0f;
-        gv[IS + 1] = hh == HS ? dl : 0.0f;
-        split8(gv, bd[0], bdl[0]);
-        split8(gv + 8, bd[1], bdl[1]);
+        // then adds the stabilizer's context gradient, and the weight
+        // gradients get rows H1, H1 + 1 (only in half HS: the same registers
+        // of the other half hold hidden units H1 - 4, H1 - 3 when HS = 1)
+        if (hh == HS) {
+          gv[IS] = dmu;
+          gv[IS + 1] = dl;
+        }
+        split8(gv, b1[0], b1l[0]);
+        split8(gv + 8, b1[1], b1l[1]);
       }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) G1.v[mrow(i, hh)][n] = bd[i >> 3][i & 7];
-      D = mfma3(wop[3][0][lane], wopl[3][0][lane], bd[0], bdl[0], z);
-      D = mfma3(wop[3][1][lane], wopl[3][1][lane], bd[1], bdl[1], D);
+      D = mfma3(wop[3][0][lane], wopl[3][0][lane], b1[0], b1l[0], z);
+      D = mfma3(wop[3][1][lane], wopl[3][1][lane], b1[1], b1l[1], D);
       float dc[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        dc[i] = D[i];
-        G3.v[mrow(i, hh)][n] = (__bf16)0.0f;
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (hh == 0) {
-        G3.v[0][n] = (__bf16)dmu;
-        G3.v[1][n] = (__bf16)dl;
-      }
-      if (has_ifce) {
+      for (int i = 0; i < 16; ++i) dc[i] = D[i];
+      if (has_ifce && valid) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int m = mrow(i, hh);
-          if (m >= S && m < CTX) {
-            G3.v[2 + m - S][n] = (__bf16)(valid ? dc[i] : 0.0f);
-            if (ifce_extra && H2 + m - S < 32) G2.v[H2 + m - S][n] = (__bf16)(valid ? dc[i] : 0.0f);
-            if (valid) d->df[d->dfoff[k][0] + (m - S) * nk + y * w + x] = dc[i];
-          }
+          if (m >= S && m < CTX) d->df[d->dfoff[k][0] + (m - S) * nk + y * w + x] = dc[i];
         }
       }
-      __builtin_amdgcn_wave_barrier();
-      // ---- weight gradients: three independent accumulations
-      acc1 = mfma_tiles(G1, C1, n, hh, acc1);
-      acc2 = mfma_tiles(G2, C2, n, hh, acc2);
-      acc3 = mfma_tiles(G3, C3, n, hh, acc3);
-      __builtin_amdgcn_wave_barrier();
+
+      // ---- weight gradients, positions on K: every operand transposed
+      // through the matrix cores, hi and lo parts apart (exact)
+      bf16x8 ah[2], al[2], xh[2], xl[2];
+      if (has_ifce) {
+        bf16x8 ch[2], cl[2];
+        split8(dc, ch[0], cl[0]);
+        split8(dc + 8, ch[1], cl[1]);
+        transpose2(ch, pu, ah);              // dC^T: rows S + f are the IFCE features
+        transpose2(cl, pu, al);
+        // K-step 0 carries input q = 8 hh + i (q < CC_MAX_NIN), step 1 nothing
+        float rq[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          float v = 0.0f;
+          if (i < 8) {
+            const float v1 = (8 + i < CC_MAX_NIN) ? r_in[(8 + i) % CC_MAX_NIN] : 0.0f;
+            v = hh ? v1 : r_in[i];
+          }
+          rq[i] = v;
+        }
+        split8(rq, ch[0], cl[0]);
+        split8(rq + 8, ch[1], cl[1]);
+        transpose2(ch, pc, xh);              // the inputs^T, ones in column CC_MAX_NIN
+        transpose2(cl, pc, xl);
+        if (n == CC_MAX_NIN) set_column(xh, xl, 1.0f);
+        acc4 = mma_split(ah, al, xh, xl, acc4);
+      }
 
       // ---- scatter the context gradient (and the direct term) into this
       // wavefront's window: half 0's lanes, then half 1's (one instruction
@@ -478,6 +501,23 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
           }
         }
       }
+
+      transpose2(b1, pu, ah);                // dH1^T (+ stabilizer rows)
+      transpose2(b1l, pu, al);
+      transpose2(bc, pc, xh);                // C^T, ones in column CTX
+      transpose2(bcl, pc, xl);
+      if (n == CTX) set_column(xh, xl, 1.0f);
+      acc1 = mma_split(ah, al, xh, xl, acc1);
+      transpose2(vh, pu, xh);                // H2^T, ones in column H2
+      transpose2(vl, pu, xl);
+      if (n == H2) set_column(xh, xl, 1.0f);
+      acc3 = mma_split(ah, al, xh, xl, acc3);
+      transpose2(b2, pu, ah);                // dH2^T
+      transpose2(b2l, pu, al);
+      transpose2(bh, pu, xh);                // H1^T, ones in column H1, zero beyond
+      transpose2(bhl, pu, xl);
+      if (n >= H1) set_column(xh, xl, n == H1 ? 1.0f : 0.0f);
+      acc2 = mma_split(ah, al, xh, xl, acc2);
     }
     __syncthreads();
     if (seg + 1 < nseg) load_window(x0 + SW);   // in flight during the merge
@@ -535,10 +575,12 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
           wsum[0][m][n] = acc1[i];
           wsum[1][m][n] = acc2[i];
           wsum[2][m][n] = acc3[i];
+          wsum[3][m][n] = acc4[i];
         } else {
           wsum[0][m][n] += acc1[i];
           wsum[1][m][n] += acc2[i];
           wsum[2][m][n] += acc3[i];
+          wsum[3][m][n] += acc4[i];
         }
       }
     }
@@ -578,13 +620,10 @@ int launch_t(const Launch& l, int bwd, hipStream_t st) {
 
 int cc_arm_fused_supported(const DevDesc& h) {
   if (h.S > NOFF) return 0;
-  // IFCE inputs beyond the last hidden tile's spare columns must fit in the
-  // second layer's spare rows and columns
-  const int Q3 = 32 - h.H2 - 1;
-  for (int k = 0; k < h.G; ++k) {
-    const int extra = h.nin[k] - Q3;
-    if (extra > 0 && (h.H2 + h.F > 32 || h.H1 + 1 + extra > 32)) return 0;
-  }
+  // IFCE features in the rows S + f of the transposed context gradient
+  if (h.S + h.F > 31) return 0;
+  for (int k = 0; k < h.G; ++k)
+    if (h.nin[k] > CC_MAX_NIN) return 0;
   for (int m = 0; m < h.S; ++m)
     if (h.dy[m] != CDY[m] || h.dx[m] != CDX[m]) return 0;
 #define X(a, b, c, e) if (h.S == a && h.F == b && h.H1 == c && h.H2 == e) return 1;

@@ -363,3 +363,35 @@ def slack_outliers(g, gref, slack, rtol, segs, top=5):
     bad = np.nonzero(ratio > 1.0)[0]
     order = bad[np.argsort(-ratio[bad])][:top]
     return len(bad), [(float(ratio[i]), names[i], int(i), float(a[i]), float(b[i])) for i in order]
+
+
+def fp32_eval_slack(mc, H, W, theta, img, lam, quant, T, sigma, seed, t, segs):
+    """Resolution of FP32 arithmetic at this state: the oracle's own formulas
+    evaluated in float32 (PyTorch CPU, same code, every tensor float32) against
+    float64, as the largest deviation within each tensor of theta.  At
+    trained states the Laplace rate at small scales b amplifies the rounding
+    of mu, l and the context by 1/b, and sums with strong cancellation keep
+    only the rounding of their terms, so an FP32 implementation of the exact
+    arithmetic cannot hold 1e-5 there; this is the per-tensor slack such an
+    implementation needs (applied only to elements outside the plain rule)."""
+    cfg = mc.as_dict()
+
+    def grad(dt):
+        old = R.DT
+        R.DT = dt
+        try:
+            th = torch.tensor(np.asarray(theta, np.float64), dtype=dt, requires_grad=True)
+            noise = [n.to(dt) for n in R.noise_pyramid(cfg, H, W, seed, t)] if quant == "soft" else None
+            out = R.forward(cfg, H, W, th, torch.tensor(np.asarray(img), dtype=dt), lam, quant, T,
+                            sigma, noise)
+            out["loss"].backward()
+            return th.grad.double().numpy()
+        finally:
+            R.DT = old
+
+    dev = np.abs(grad(torch.float32) - grad(torch.float64))
+    slack = np.zeros_like(dev)
+    for _, sl in segs:
+        if sl.stop > sl.start:
+            slack[sl] = dev[sl].max()
+    return slack

@@ -1,14 +1,16 @@
 """Fused BF16 form against the FP64 CPU oracle.
 
-Rule: MLP operands in BF16 (8-bit mantissa) with FP32 accumulation, rate
-arithmetic in FP32, totals in FP64.  Per step from the same state: totals
-(loss, bits, MSE) within 1e-3 relative; every gradient element within
-|gpu - oracle| <= rtol (|oracle| + rms(oracle over its tensor)), rtol = 2e-2.
-BF16 rounding of the context moves ARM pre-activations by ~0.4% of their
-terms, so ReLU decisions near zero flip far more often than in FP32; the
-elements behind them (weight rows of the flipped units) are counted: at most
-0.1% of the gradient on the workload states, 1% on the random stress states
-(whose larger latents and untrained output layer put more units near zero).
+Rule: MLP operands in BF16 with FP32 accumulation (the ARM's data-path
+products in split BF16, its weight gradients in plain BF16), rate arithmetic
+in FP32, totals in FP64.  Per step from the same state: totals (loss, bits,
+MSE) within 1e-3 relative; every gradient element within
+|gpu - oracle| <= rtol (|oracle| + rms(oracle over its tensor)) + slack,
+rtol = 2e-2, where slack is the change of the oracle gradient when a ReLU,
+log-scale clamp or probability-floor decision whose argument lies within
+BF16 resolution of its threshold (3e-5 of the layer's rms; split operands
+carry about 16 significant bits) is inverted, summed over such decisions
+(the same mechanism as the FP32 rule, tests/gpu_util.py: decision_slack).
+No element may fall outside.
 """
 import numpy as np
 import pytest
@@ -17,12 +19,13 @@ import torch
 from oracle import coolchic_ref as R
 from paper_2605_02726_amd import workloads as wl
 
-from gpu_util import outliers, segments
+from gpu_util import decision_slack, outliers, segments, slack_outliers
 
 pytestmark = pytest.mark.gpu
 
 RTOL = 2e-2
 TOT = 1e-3
+TAU = 3e-5   # near-threshold distance at BF16 resolution, relative to the layer's rms
 
 def _with_conv(mc):
     mc.ups_conv = 1
@@ -82,15 +85,22 @@ def test_bf16_first_step(case):
     g = enc.grad()
     ref = R.loss_and_grad(mc.as_dict(), H, W, np.concatenate([lat, par]).astype(np.float64),
                           img, lam, "soft", T, sigma, seed, 1)
-    n_bad, worst = outliers(g, ref[3], RTOL, segments(mc, H, W))
+    segs = segments(mc, H, W)
+    n_plain, worst = outliers(g, ref[3], RTOL, segs)
+    n_bad, n_near, n_used = 0, 0, 0
+    if n_plain:
+        theta = np.concatenate([lat, par]).astype(np.float64)
+        _, slack, n_near, n_used = decision_slack(mc, H, W, theta, img, lam, "soft", T, sigma,
+                                                  seed, 1, tau=TAU, max_sites=64)
+        n_bad, worst = slack_outliers(g, ref[3], slack, RTOL, segs)
     print(f"[{case}] loss {loss:.7g}/{ref[0]:.7g} bits {bits:.8g}/{ref[1]:.8g} "
-          f"({(bits / ref[1] - 1):.2e}) mse {mse:.7g}/{ref[2]:.7g}; gradient {n_bad} of {g.size} "
-          f"outside rtol {RTOL}; worst {worst}", flush=True)
+          f"({(bits / ref[1] - 1):.2e}) mse {mse:.7g}/{ref[2]:.7g}; gradient {n_plain} of {g.size} "
+          f"outside rtol {RTOL}, {n_near} near-threshold decisions ({n_used} used), {n_bad} "
+          f"outside with their slack; worst {worst}", flush=True)
     assert bits == pytest.approx(ref[1], rel=TOT)
     assert mse == pytest.approx(ref[2], rel=TOT)
     assert loss == pytest.approx(ref[0], rel=TOT)
-    allowed = (1e-2 if CASES[case][4] else 1e-3) * g.size
-    assert n_bad <= allowed
+    assert n_bad == 0
 
 
 def test_bf16_rd_eval_and_decode():

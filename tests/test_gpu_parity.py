@@ -267,13 +267,14 @@ def test_largest_serving_image(precision):
     latents), from a random state: totals and every gradient element against
     the oracle.  At this size about a thousand ReLU, clamp and floor
     decisions sit within rounding of their thresholds, too many to recompute
-    the whole oracle once per decision.  In FP32 every latent element outside
-    the per-element rule must lie inside the footprint of such a decision
+    the whole oracle once per decision.  Every latent element outside the
+    per-element rule must lie inside the footprint of such a decision
     (`unexplained_outliers`; the footprints cover about 0.5% of grid 0), and
     every decoder-parameter element must hold the rule plus the first-order
     slack of those decisions (`param_flip_slack`: each decision's own term
-    recomputed with the decision inverted).  The BF16 form is held to its own
-    rule (2e-2, at most 1% of the elements outside on random states)."""
+    recomputed with the decision inverted).  FP32: rtol 1e-5, decisions
+    within 3e-6 of the layer's rms; BF16: rtol 2e-2, decisions within 3e-5
+    (the resolution of its split operands)."""
     mc = wl.config_hop()
     H = W = 2048
     seed = 21
@@ -287,33 +288,31 @@ def test_largest_serving_image(precision):
     theta = np.concatenate([lat, par]).astype(np.float64)
     if "ref" not in _LARGEST:     # one oracle run (~20 s, ~15 GB) serves both forms
         tot, cap = {}, {}
-        gref, sites = _oracle_grad(mc, H, W, theta, img, lam, "soft", T, sigma, seed, t, 3e-6,
+        gref, sites = _oracle_grad(mc, H, W, theta, img, lam, "soft", T, sigma, seed, t, 3e-5,
                                    set(), totals=tot, capture=cap)
         _LARGEST["ref"] = (tot, gref, sites, cap)
     tot, gref, sites, cap = _LARGEST["ref"]
-    tol_tot = RTOL if precision == "fp32" else 1e-3
+    rtol, tol_tot = (RTOL, RTOL) if precision == "fp32" else (2e-2, 1e-3)
+    if precision == "fp32":   # decisions within 3e-6 of the layer's rms
+        sites = [e for e in sites if e[0] < 0.1]
     print(f"[2048x2048/{precision}] loss {loss:.9g} vs {tot['loss']:.9g}; bits {bits:.9g} vs "
           f"{tot['bits']:.9g}; mse {mse:.9g} vs {tot['mse']:.9g}", flush=True)
     assert loss == pytest.approx(tot["loss"], rel=tol_tot)
     assert bits == pytest.approx(tot["bits"], rel=tol_tot)
     assert mse == pytest.approx(tot["mse"], rel=tol_tot)
     segs = segments(mc, H, W)
-    if precision == "fp32":
-        n_lat = enc.n_lat
-        bad = outlier_indices(g, gref, RTOL, segs)
-        left = unexplained_outliers(mc, H, W, bad[bad < n_lat], sites)
-        slack = np.zeros(g.size)
+    n_lat = enc.n_lat
+    bad = outlier_indices(g, gref, rtol, segs)
+    left = unexplained_outliers(mc, H, W, bad[bad < n_lat], sites)
+    slack = np.zeros(g.size)
+    psegs = [sg for sg in segs if sg[1].start >= n_lat]
+    n_par_bad, worst = slack_outliers(g, gref, slack, rtol, psegs)
+    if n_par_bad:   # only then are the decisions' parameter terms needed
         slack[n_lat:] = param_flip_slack(mc, H, W, theta, lam, sites, cap)
-        n_par_bad, worst = slack_outliers(g, gref, slack, RTOL,
-                                          [sg for sg in segs if sg[1].start >= n_lat])
-        print(f"[2048x2048/fp32] {len(bad)} of {g.size} elements outside the rule, "
-              f"{len(sites)} near-threshold decisions; latents outside every footprint: "
-              f"{len(left)} {left[:8]}; parameters outside rule + slack: {n_par_bad} {worst}",
-              flush=True)
-        assert not left
-        assert n_par_bad == 0
-    else:
-        n_out, worst = outliers(g, gref, 2e-2, segs)
-        print(f"[2048x2048/bf16] {n_out} of {g.size} elements outside the rule; worst {worst}",
-              flush=True)
-        assert n_out <= 1e-2 * g.size
+        n_par_bad, worst = slack_outliers(g, gref, slack, rtol, psegs)
+    print(f"[2048x2048/{precision}] {len(bad)} of {g.size} elements outside the rule, "
+          f"{len(sites)} near-threshold decisions; latents outside every footprint: "
+          f"{len(left)} {left[:8]}; parameters outside rule + slack: {n_par_bad} {worst}",
+          flush=True)
+    assert not left
+    assert n_par_bad == 0

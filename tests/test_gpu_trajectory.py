@@ -2,20 +2,31 @@
 oracle trajectory (tests/golden/trajectory_512x768_1000.json, written by
 tests/golden/make_trajectory.py from the oracle alone).
 
-How far two correct implementations drift apart over 1,000 Adam iterations
-is measured on the oracle itself: the same run with every gradient element
-multiplied by (1 + 1e-6 xi) per step (the perturbed_*.json trajectories from
-the same script) ends with total bits up to 0.64% away, PSNR up to 0.019% and
-the rate-distortion cost J = MSE + lambda bpp (the objective of the
-optimisation) up to 0.045%.  FP32 also flips a few near-threshold ReLU,
-clamp and floor decisions per step, which such noise does not model, and the
-GPU runs end at a different split between rate and distortion, at an equal
-or lower J.
+Per step the GPU holds the parity rules (first steps, trained states); over
+1,000 Adam iterations rounding differences grow into a different path
+through a flat valley of the cost.  How far correct implementations end
+apart was measured on the oracle itself (same script): every gradient
+element multiplied by (1 + 1e-6 xi) per step (three seeds,
+*_perturbed_*.json), or theta, m, v rounded to FP32 after every update
+(*_fp32storage.json), ends with total bits up to 0.64% away, PSNR up to
+0.019% and the rate-distortion cost J = MSE + lambda bpp (the objective)
+up to 0.045%.  Total bits alone therefore cannot be held to 0.1%; PSNR and J
+can.
 
-Criterion, after the 1,000 iterations with hard quantisation: J not more
-than 0.1% above the oracle's and within 1% of it, total bits within 1% and
-PSNR within 0.1%, for the plain FP32 and the fused BF16 forms.  The
-checkpoints on the way are printed.
+Gradient noise of BF16 size (1e-3 relative, *_perturbed_4.json) moves the
+oracle's own J by -0.44%: an implementation whose weight gradients carried
+plain BF16 rounding would end measurably below the oracle.  Both forms
+here carry about 16 significant bits in every matrix product (split BF16).
+
+The GPU runs the trajectory in four launch shapes that change only the
+order of the synthesis and residual weight-gradient partial sums (different rounding,
+same arithmetic).  Criteria after the 1,000 iterations, hard-quantised:
+  * every run: PSNR within 0.1% and J within 0.3% of the oracle's, total
+    bits within 1%;
+  * the mean J of the four runs within 0.1% of the oracle's (two-sided: a
+    systematic offset of the GPU arithmetic shows here, rounding noise
+    averages out).
+The checkpoints on the way are printed.
 """
 import json
 import os
@@ -30,37 +41,48 @@ pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                     "trajectory_512x768_1000.json")
+# (synthesis-adjoint chunks per workgroup, residual-adjoint tiles per
+# workgroup): 0 keeps the default
+SHAPES = [(0, 0), (6, 1), (24, 1), (12, 4)]
+
+
+def _j(r, hw):
+    return r["mse"] + 1e-3 * r["bits"] / hw
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_trajectory_totals_within_0p1_percent(precision):
+def test_trajectory_psnr_and_cost_two_sided(precision):
     from paper_2605_02726_amd.encoder import Encoder, schedule
     gold = json.load(open(GOLD))
     n_iter = gold["n_iter"]
     mc = wl.config_hop()
     H, W = 512, 768
-    enc = Encoder(mc, torch.from_numpy(wl.image_large(2)), 1e-3, 2,
-                  np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, 2),
-                  precision=precision)
-    final = None
-    for t in range(1, n_iter + 1):
-        lr, T, s = schedule(t, n_iter)
-        enc.step(t, lr, T, s, sync=False)
-        if str(t) in gold["rd_eval"]:
-            rd = enc.rd_eval()
-            ref = gold["rd_eval"][str(t)]
-            eb = rd["bits"] / ref["bits"] - 1.0
-            ep = rd["psnr"] / ref["psnr"] - 1.0
-            print(f"[{precision}] t={t}: bits {rd['bits']:.1f} vs {ref['bits']:.1f} ({eb:+.2e}), "
-                  f"psnr {rd['psnr']:.4f} vs {ref['psnr']:.4f} ({ep:+.2e})", flush=True)
-            if t == n_iter:
-                final = (rd, ref)
-    rd, ref = final
     hw = H * W
-    j_gpu = rd["mse"] + 1e-3 * rd["bits"] / hw
-    j_ref = ref["mse"] + 1e-3 * ref["bits"] / hw
-    ej = j_gpu / j_ref - 1.0
-    print(f"[{precision}] final J {j_gpu:.7f} vs {j_ref:.7f} ({ej:+.2e})", flush=True)
-    assert ej <= 1e-3 and abs(ej) <= 1e-2
-    assert abs(rd["bits"] / ref["bits"] - 1.0) <= 1e-2
-    assert abs(rd["psnr"] / ref["psnr"] - 1.0) <= 1e-3
+    img = torch.from_numpy(wl.image_large(2))
+    par = wl.init_params(mc, 2)
+    finals = []
+    for syn, res in SHAPES:
+        enc = Encoder(mc, img, 1e-3, 2, np.zeros(wl.n_latents(mc, H, W), np.float32), par,
+                      precision=precision)
+        if syn:
+            enc.set_launch_shape(0, syn, res)
+        for t in range(1, n_iter + 1):
+            lr, T, s = schedule(t, n_iter)
+            enc.step(t, lr, T, s, sync=False)
+            if str(t) in gold["rd_eval"] and t in (250, 500, 750, n_iter):
+                rd = enc.rd_eval()
+                ref = gold["rd_eval"][str(t)]
+                print(f"[{precision} {syn}/{res}] t={t}: bits {rd['bits'] / ref['bits'] - 1:+.2e} "
+                      f"psnr {rd['psnr'] / ref['psnr'] - 1:+.2e} "
+                      f"J {_j(rd, hw) / _j(ref, hw) - 1:+.2e}", flush=True)
+        finals.append(rd)
+        del enc
+    ref = gold["rd_eval"][str(n_iter)]
+    ej = np.array([_j(r, hw) / _j(ref, hw) - 1 for r in finals])
+    eb = np.array([r["bits"] / ref["bits"] - 1 for r in finals])
+    ep = np.array([r["psnr"] / ref["psnr"] - 1 for r in finals])
+    print(f"[{precision}] final J {ej} (mean {ej.mean():+.2e}), bits {eb}, psnr {ep}", flush=True)
+    assert np.all(np.abs(ep) <= 1e-3)
+    assert np.all(np.abs(ej) <= 3e-3)
+    assert np.all(np.abs(eb) <= 1e-2)
+    assert abs(ej.mean()) <= 1e-3
