@@ -33,17 +33,69 @@ PEAKS = {
     "fp32_valu_TFLOPs": 78.6,
 }
 
-# HBM bytes per launch of the fused BF16 ARM kernel on the 512x768 workload,
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by a plain-copy
-# calibration (FETCH x2.000, WRITE x1.000); the commands and the table are in
-# profiles/hbm_traffic_bf16_512x768.txt.  Set to None when the kernel changes
-# until the counters are taken again.
-ARM_FUSED_TRAFFIC_BYTES = int((1.9999 * 3609.9 + 1.0 * 18673.3) * 1024)
-# Wave-level VALU instructions and MFMA-busy fraction per launch of the same
-# kernel (SQ_INSTS_VALU, MfmaUtil), from the counter pass in
-# profiles/mfma_valu_activity_bf16_512x768.txt; None when the kernel changes.
-ARM_FUSED_VALU_INSTS = 1.748e7
-ARM_FUSED_MFMA_UTIL = 0.0399
+# Counter figures of the fused BF16 ARM kernel come from the committed
+# rocprofv3 summaries, never from constants here: the HBM traffic from the
+# FETCH_SIZE / WRITE_SIZE table (scaled by its plain-copy calibration) and the
+# VALU / MFMA activity from the SQ counter table.  Each summary names the
+# kernel source it was taken from and that file's SHA-256; when the source
+# has changed since, the figure is reported as null.
+ARM_FUSED_SRC = os.path.join("paper_2605_02726_amd", "csrc", "k_arm_fused.hip")
+ARM_TRAFFIC_PROFILE = os.path.join("profiles", "hbm_traffic_bf16_512x768.txt")
+ARM_ACTIVITY_PROFILE = os.path.join("profiles", "mfma_valu_activity_bf16_512x768.txt")
+
+
+def _source_sha(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def read_profile_row(rel, kernel_prefix):
+    """(header fields, row fields) of the kernel's row in a committed counter
+    table, and whether its recorded source hash matches the current source.
+    Returns None when the file or the row is missing."""
+    path = os.path.join(ROOT, rel)
+    if not os.path.exists(path):
+        return None
+    head, row, src_ok, scale = None, None, False, {}
+    for line in open(path):
+        t = line.strip()
+        if t.startswith("kernel source:"):
+            parts = t.split()
+            src_ok = len(parts) >= 4 and parts[3] == _source_sha(parts[2])
+        elif t.startswith("scale factors:"):
+            for part in t[len("scale factors:"):].split(","):
+                name, _, fac = part.strip().partition(" x")
+                scale[name] = float(fac)
+        elif t.startswith("kernel ") and head is None:
+            head = t.split()[1:]
+        elif t.startswith(kernel_prefix) and head is not None and row is None:
+            rest = t[t.index(">") + 1:].split() if ">" in t else t.split()[1:]
+            row = dict(zip(head, rest))
+    if row is None:
+        return None
+    return {"row": row, "current": src_ok, "scale": scale, "file": rel}
+
+
+def arm_counters():
+    """Traffic (bytes per launch) and activity of the fused ARM kernel from the
+    committed summaries; None entries when stale or missing."""
+    out = {"traffic": None, "valu_insts": None, "mfma_util": None, "notes": []}
+    tr = read_profile_row(ARM_TRAFFIC_PROFILE, "k_arm_fused<24, 6, 24, 24>")
+    if tr and tr["current"]:
+        r, sc = tr["row"], tr["scale"]
+        out["traffic"] = int((sc["FETCH"] * float(r["FETCH_KiB"]) + sc["WRITE"] * float(r["WRITE_KiB"])) * 1024)
+        out["notes"].append(tr["file"])
+    else:
+        out["notes"].append(f"{ARM_TRAFFIC_PROFILE}: missing or taken from another kernel source")
+    ac = read_profile_row(ARM_ACTIVITY_PROFILE, "k_arm_fused<24, 6, 24, 24>")
+    if ac and ac["current"]:
+        out["valu_insts"] = float(ac["row"]["INSTS_VALU"])
+        out["mfma_util"] = float(ac["row"]["MFMA_util"].rstrip("%")) / 100.0
+        out["notes"].append(ac["file"])
+    else:
+        out["notes"].append(f"{ARM_ACTIVITY_PROFILE}: missing or taken from another kernel source")
+    return out
 
 
 def arm_flops_per_step(mc, H, W):
@@ -300,11 +352,48 @@ def measure_serving(n_req, n_iter, rate_hz=8.0, precision="bf16"):
     srv.run(jobs)
     st = srv.stats()
     mean_px = float(np.mean([j.image.shape[1] * j.image.shape[2] for j in jobs]))
-    st.update({"requests": n_req, "iterations_per_request": n_iter, "rate_hz": rate_hz,
+    st.update({"requests": n_req, "iterations_per_request": n_iter, "rate_hz": round(rate_hz, 4),
                "offered_mpx_it_s": rate_hz * n_iter * mean_px / 1e6,
                "sides": "multiples of 64 in [256, 2048]", "lambdas": [1e-4, 4e-4, 1e-3, 4e-3],
                "precision": precision})
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+
+
+def serving_oracle_check(n_req, rate_hz, n_iter=20, n_check=2, precision="bf16"):
+    """Per-request error against the FP64 oracle on a sampled subset: the
+    n_check smallest requests of the trace, served together (continuous
+    batching, their own arrival times) for n_iter iterations each, and each
+    encoded alone by the oracle with the same schedule; hard-quantised total
+    bits and PSNR compared."""
+    import numpy as np
+    import torch
+    from oracle import coolchic_ref as R
+    from paper_2605_02726_amd import workloads as wl
+    from paper_2605_02726_amd.serve import Server, trace_jobs
+
+    mc = wl.config_hop()
+    jobs = trace_jobs(n_req, rate_hz, seed=7, lo=256, hi=2048, n_iter=n_iter, mc=mc)
+    jobs = sorted(jobs, key=lambda j: j.image.shape[1] * j.image.shape[2])[:n_check]
+    base = min(j.arrival for j in jobs)
+    for j in jobs:
+        j.arrival -= base
+    srv = Server(mc, precision=precision, check_every=50)
+    done = srv.run(jobs)
+    torch.set_num_threads(os.cpu_count() or 1)
+    out = []
+    for j in done:
+        _, H, W = j.image.shape
+        ost = R.OracleState(mc.as_dict(), H, W, j.image, j.lam, j.seed,
+                            np.zeros(wl.n_latents(mc, H, W), np.float32), j.params)
+        for t in range(1, n_iter + 1):
+            ost.step(t, *R.schedule(t, n_iter))
+        ref = ost.rd_eval()
+        out.append({"request": j.rid, "size": f"{H}x{W}", "lambda": j.lam,
+                    "bits_rel_err": round(j.result["bits"] / ref["bits"] - 1, 7),
+                    "psnr_rel_err": round(j.result["psnr"] / ref["psnr"] - 1, 7)})
+    return {"iterations": n_iter, "precision": precision, "requests": out,
+            "note": "the smallest requests of the below-capacity trace, served together; "
+                    "oracle run alone per request"}
 
 
 def main():
@@ -316,6 +405,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=36, help="oracle steps for cpu_baseline (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=20, help="batched-step timing (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=16, help="serving trace length (0 = skip)")
+    ap.add_argument("--serve-light-requests", type=int, default=8,
+                    help="requests of the below-capacity serving trace (0 = skip)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="time only the 16-image batched step (for profiler runs)")
     ap.add_argument("--serve-iters", type=int, default=2000)
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -331,10 +424,15 @@ def main():
     if args.copy_calibration:
         print(json.dumps(copy_calibration()))
         return
+    if args.only_batch:
+        import torch  # noqa: F401
+        print(json.dumps({"batched_16_images": measure_batch(args.batch_steps or 20, 3)}))
+        return
     if args.only_step:
         args.no_soap = True
         args.batch_steps = 0
         args.serve_requests = 0
+        args.serve_light_requests = 0
         args.cpu_steps = 0
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU: the per-image encode step is "
@@ -403,20 +501,22 @@ def main():
         avg_s = main_f["arm_avg_ms"] / 1e3
         achieved = flops / avg_s / 1e12
         peak = PEAKS["bf16_mfma_TFLOPs"] if head == "bf16" else PEAKS["fp32_valu_TFLOPs"]
+        ctr = arm_counters() if head == "bf16" else None
         roof = {"kernel": "arm_fused_fwd_rate_bwd" if head == "bf16" else "arm_plain_fwd_rate_bwd",
                 "bound": "mfma" if head == "bf16" else "alu", "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-                "traffic": ARM_FUSED_TRAFFIC_BYTES if head == "bf16" else None,
+                "traffic": ctr["traffic"] if ctr else None,
                 "traffic_unit": "bytes per launch", "avg_launch_ms": round(1e3 * avg_s, 4),
                 "flops_per_launch": flops}
-        if head == "bf16" and ARM_FUSED_VALU_INSTS:
+        if ctr:
+            roof["counters_from"] = ctr["notes"]
+        if ctr and ctr["valu_insts"]:
             # what bounds it instead: the vector pipes issue a wave-level
             # instruction every 4 cycles per SIMD (256 CUs x 4 SIMDs, 2.4 GHz)
-            valu_s = ARM_FUSED_VALU_INSTS * 4 / (256 * 4 * 2.4e9)
-            roof["issue"] = {"valu_insts_per_launch": ARM_FUSED_VALU_INSTS,
+            valu_s = ctr["valu_insts"] * 4 / (256 * 4 * 2.4e9)
+            roof["issue"] = {"valu_insts_per_launch": ctr["valu_insts"],
                              "valu_issue_frac": round(valu_s / avg_s, 4),
-                             "mfma_busy_frac": ARM_FUSED_MFMA_UTIL,
-                             "note": "counters: profiles/mfma_valu_activity_bf16_512x768.txt"}
+                             "mfma_busy_frac": ctr["mfma_util"]}
         if "arm_avg_ms" in serial:
             a1 = flops / (serial["arm_avg_ms"] / 1e3) / 1e12
             roof["kernel_alone"] = {"achieved": round(a1, 3), "frac": round(a1 / peak, 5),
@@ -443,6 +543,21 @@ def main():
         hbm["join"]["note"] = "latent join + Adam and the first weight-gradient reduction pass (one launch)"
     batched = measure_batch(args.batch_steps, 3) if args.batch_steps > 0 else None
     serving = measure_serving(args.serve_requests, args.serve_iters) if args.serve_requests > 0 else None
+    if serving is not None and args.serve_light_requests > 0:
+        # a second trace offered at about 0.8 of the measured batched capacity,
+        # so that p50/p99 measure service rather than queueing, and the
+        # per-request oracle check on its smallest requests
+        import numpy as np
+        from paper_2605_02726_amd.serve import trace_jobs
+        cap = (batched or {}).get("value") or serving["throughput_mpx_it_s"]
+        probe = trace_jobs(args.serve_light_requests, 1.0, seed=7, lo=256, hi=2048,
+                           n_iter=args.serve_iters)
+        mean_px = float(np.mean([j.image.shape[1] * j.image.shape[2] for j in probe]))
+        rate = 0.8 * cap * 1e6 / (args.serve_iters * mean_px)
+        light = measure_serving(args.serve_light_requests, args.serve_iters, rate_hz=rate)
+        light["offered_fraction_of_capacity"] = round(light["offered_mpx_it_s"] / cap, 3)
+        serving = {"overloaded": serving, "below_capacity": light,
+                   "oracle_check": serving_oracle_check(args.serve_light_requests, rate)}
 
     cpu = None
     if args.cpu_steps > 0:

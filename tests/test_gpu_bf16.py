@@ -1,7 +1,7 @@
 """Fused BF16 form against the FP64 CPU oracle.
 
 Rule: MLP operands in BF16 with FP32 accumulation (the ARM's data-path
-products in split BF16, its weight gradients in plain BF16), rate arithmetic
+products and weight gradients in split BF16), rate arithmetic
 in FP32, totals in FP64.  Per step from the same state: totals (loss, bits,
 MSE) within 1e-3 relative; every gradient element within
 |gpu - oracle| <= rtol (|oracle| + rms(oracle over its tensor)) + slack,

@@ -81,3 +81,30 @@ def test_server_cancels_only_the_nonfinite_request():
         assert done[rid].status == "done"
         ref, _ = _alone(mc, done[rid], "bf16")
         assert done[rid].result == ref
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_server_requests_follow_the_oracle(precision):
+    """Per-request rate and distortion of requests served in a mix (different
+    sizes, lambdas, arrival times) against the FP64 oracle encoding each
+    request alone with the same schedule: total bits and PSNR of the
+    hard-quantised result within 1e-4 relative after the request's 40
+    iterations (Table I schedules mapped onto its budget)."""
+    from oracle import coolchic_ref as R
+    from paper_2605_02726_amd.serve import Server
+    mc, jobs = _jobs(n_iter=40)
+    srv = Server(mc, precision=precision, check_every=10)
+    done = srv.run(jobs)
+    for j in done:
+        assert j.status == "done"
+        _, H, W = j.image.shape
+        ost = R.OracleState(mc.as_dict(), H, W, j.image, j.lam, j.seed,
+                            np.zeros(wl.n_latents(mc, H, W), np.float32), j.params)
+        for t in range(1, j.n_iter + 1):
+            ost.step(t, *R.schedule(t, j.n_iter))
+        ref = ost.rd_eval()
+        eb = j.result["bits"] / ref["bits"] - 1
+        ep = j.result["psnr"] / ref["psnr"] - 1
+        print(f"[{precision}] request {j.rid} {H}x{W} lambda {j.lam:g}: bits {eb:+.2e} psnr {ep:+.2e}",
+              flush=True)
+        assert abs(eb) <= 1e-4 and abs(ep) <= 1e-4

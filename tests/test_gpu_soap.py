@@ -9,7 +9,10 @@ checked per step from a shared state taken after a few dozen oracle steps
 (generic factors, distinct eigenvalues), on an ordinary update and on a
 basis-refresh update.  Rule: gradients agree to 1e-5 (the step parity
 rule), so the SOAP quantities (moments, factors, parameter update) are held
-to 1e-4 per element, relative to the element plus the rms of its array."""
+to 1e-4 per element, relative to the element plus the rms of its array.  The
+fused BF16 form is checked in two parts: its gradient against the oracle's
+at the BF16 step rule, and its SOAP step against the oracle's SOAP fed with
+that same gradient."""
 import numpy as np
 import pytest
 import torch
@@ -100,6 +103,24 @@ def _oracle_after(mc, H, W, img, lat, par, seed, lam, n_steps, n_iter=200):
     return ora
 
 
+def _close_refreshed(mc, lay, q_before, q_gpu, ex2):
+    """Refreshed bases: Q = qr(P Q_sorted) is unique up to column signs, but
+    the columns that Gram-Schmidt reaches after R's diagonal has dropped
+    below 1e-4 of its first entry span a near-null subspace of the factor
+    and are fixed by rounding; the leading columns before that point are
+    compared."""
+    old = _factors(mc, lay, q_before)
+    for (name, d, qg), (_, _, qo), (_, _, po), (_, _, q0) in zip(
+            _factors(mc, lay, q_gpu), _factors(mc, lay, ex2["q"]),
+            _factors(mc, lay, ex2["p"]), old):
+        order = np.argsort(-np.diag(q0.T @ po @ q0), kind="stable")
+        rd = np.abs(np.diag(np.linalg.qr(po @ q0[:, order])[1]))
+        k = int(np.argmax(rd < 1e-4 * rd[0])) if np.any(rd < 1e-4 * rd[0]) else len(rd)
+        sg = np.sign(np.sum(qg * qo, axis=0))
+        print(f"refreshed basis {name}[{d}]: {k} of {len(rd)} leading columns compared", flush=True)
+        _close((qg * sg[None, :])[:, :k], qo[:, :k], 1e-3, f"refreshed basis {name}[{d}]")
+
+
 @pytest.mark.parametrize("mk", [wl.config_hop, wl.config_hop_hyper])
 @pytest.mark.parametrize("n_before", [22, 19])    # next update: s = 23 (plain), s = 20 (refresh)
 def test_one_update_from_a_shared_state(n_before, mk):
@@ -128,21 +149,55 @@ def test_one_update_from_a_shared_state(n_before, mk):
     for (name, d, pg), (_, _, po) in zip(_factors(mc, lay, gs["p"]), _factors(mc, lay, ex2["p"])):
         _close(pg, po, TOL, f"factor {name}[{d}]")
     if ex2["s"] % S.REFRESH == 0:
-        # refreshed bases: Q = qr(P Q_sorted) is unique up to column signs,
-        # but the columns that Gram-Schmidt reaches after R's diagonal has
-        # dropped below 1e-4 of its first entry span a near-null subspace of
-        # the factor and are fixed by rounding; the leading columns before
-        # that point are compared
-        old = _factors(mc, lay, ex["q"])
-        for (name, d, qg), (_, _, qo), (_, _, po), (_, _, q0) in zip(
-                _factors(mc, lay, gs["q"]), _factors(mc, lay, ex2["q"]),
-                _factors(mc, lay, ex2["p"]), old):
-            order = np.argsort(-np.diag(q0.T @ po @ q0), kind="stable")
-            rd = np.abs(np.diag(np.linalg.qr(po @ q0[:, order])[1]))
-            k = int(np.argmax(rd < 1e-4 * rd[0])) if np.any(rd < 1e-4 * rd[0]) else len(rd)
-            sg = np.sign(np.sum(qg * qo, axis=0))
-            print(f"refreshed basis {name}[{d}]: {k} of {len(rd)} leading columns compared", flush=True)
-            _close((qg * sg[None, :])[:, :k], qo[:, :k], 1e-3, f"refreshed basis {name}[{d}]")
+        _close_refreshed(mc, lay, ex["q"], gs["q"], ex2)
+
+
+@pytest.mark.parametrize("n_before", [22, 19])    # next update: s = 23 (plain), s = 20 (refresh)
+def test_bf16_update_from_a_shared_state(n_before):
+    """The fused BF16 form feeds its own gradient to the same SOAP kernel.
+    From a shared state: that gradient holds the BF16 step rule against the
+    oracle's (2e-2 of |g| + rms per element, plus the slack of decisions
+    within BF16 resolution of their thresholds), and the SOAP update, moments,
+    factors and refreshed bases equal the oracle's SOAP step fed with the
+    GPU's gradient, to the FP32 rule's 1e-4."""
+    import copy
+    from gpu_util import decision_slack, outliers, segments, slack_outliers
+    mc, H, W, img, lat, par, seed = _case()
+    lam = 1e-3
+    ora = _oracle_after(mc, H, W, img, lat, par, seed, lam, n_before + 1)
+    enc = _encoder(mc, img, lam, seed, lat, par, precision="bf16")
+    n = ora.n_lat
+    enc.set_state(latents=ora.theta[:n], params=ora.theta[n:], m=ora.m, v=ora.v, t=n_before + 1)
+    ex = ora.soap.export()
+    enc.set_soap_state(m=ex["m"], v=ex["v"], p=ex["p"], q=ex["q"], calls=ex["s"] + 1)
+    t = n_before + 2
+    lr, T, s = R.schedule(t, 200)
+    theta0 = ora.theta.copy()
+    soap_in = copy.deepcopy(ora.soap)
+    enc.step(t, lr, T, s)
+    g = enc.grad()
+    ora.step(t, lr, T, s)
+    segs = segments(mc, H, W)
+    n_plain, worst = outliers(g, ora.last_grad, 2e-2, segs)
+    n_bad = 0
+    if n_plain:
+        _, slack, _, _ = decision_slack(mc, H, W, theta0, img, lam, "soft", T, s, seed, t,
+                                        tau=3e-5, max_sites=64)
+        n_bad, worst = slack_outliers(g, ora.last_grad, slack, 2e-2, segs)
+    print(f"gradient: {n_plain} outside 2e-2, {n_bad} outside with slack; worst {worst}", flush=True)
+    assert n_bad == 0
+    new = soap_in.step(theta0[n:], np.asarray(g[n:], np.float64), lr)
+    ex2 = soap_in.export()
+    st, gs = enc.get_state(), enc.get_soap_state()
+    assert gs["calls"] == ex2["s"] + 1
+    _close(st["params"] - theta0[n:], new - theta0[n:], TOL, "parameter update")
+    _close(gs["m"], ex2["m"], TOL, "first moment")
+    _close(gs["v"], ex2["v"], TOL, "second moment")
+    lay = soap_in.layout
+    for (name, d, pg), (_, _, po) in zip(_factors(mc, lay, gs["p"]), _factors(mc, lay, ex2["p"])):
+        _close(pg, po, TOL, f"factor {name}[{d}]")
+    if ex2["s"] % S.REFRESH == 0:
+        _close_refreshed(mc, lay, ex["q"], gs["q"], ex2)
 
 
 def test_soap_batch_equals_alone():

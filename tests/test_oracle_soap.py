@@ -199,3 +199,121 @@ def test_gram_schmidt_qr_on_rank_deficient_input():
     assert np.allclose(rng_basis @ (rng_basis.T @ q[:, :r]), q[:, :r], atol=1e-10)
     # the rule is deterministic: scaling z does not change the result
     assert np.allclose(S.qr_gs(3.0 * z), q, atol=1e-10)
+
+
+def _replaced(z, q, tol=S.QR_TOL):
+    """Columns k of z that lie within tol of the span of q's first k columns."""
+    out = []
+    for k in range(z.shape[1]):
+        nz = np.linalg.norm(z[:, k])
+        res = z[:, k] - q[:, :k] @ (q[:, :k].T @ z[:, k])
+        if nz == 0.0 or np.linalg.norm(res) <= tol * nz:
+            out.append(k)
+    return out
+
+
+def _is_qr_within_tol(z, q, tol=S.QR_TOL):
+    """What any QR of z with completed columns satisfies, whatever rule picks
+    the completion: q orthonormal, and z + E = q R with R upper triangular
+    and every column of E at most tol of the column of z (R = q^T z, so E's
+    column k is the part of z_k outside the span of q's first k+1 columns);
+    R's diagonal is positive where the column was not completed, and above
+    -tol |z_k| where it was (the dropped remainder may point either way)."""
+    n = z.shape[1]
+    assert np.abs(q.T @ q - np.eye(n)).max() <= 1e-12
+    r = q.T @ z
+    rep = _replaced(z, q, tol)
+    for k in range(n):
+        nz = np.linalg.norm(z[:, k])
+        assert np.linalg.norm(r[k + 1:, k]) <= tol * nz * (1 + 1e-6) + 1e-300
+        assert r[k, k] >= -tol * nz * (1 + 1e-6) if k in rep else r[k, k] > 0.0
+
+
+def test_gram_schmidt_completion_spans_the_complement_of_the_range():
+    """Rank r with independent leading columns (the order a refresh produces
+    when the eigenvalue estimates put the range first): the first r columns
+    are the Householder QR of z's first r columns (numpy's LAPACK routine,
+    signs made positive), which is unique, and the completed columns span
+    the orthogonal complement of z's range, taken from the SVD.  Neither
+    check uses the completion rule."""
+    rng = np.random.default_rng(16)
+    for n, r in ((6, 3), (24, 22), (30, 22), (40, 25), (5, 1)):
+        a = rng.normal(size=(n, r))
+        b = np.concatenate([np.eye(r), rng.normal(size=(r, n - r))], axis=1)
+        z = a @ b
+        q = S.qr_gs(z)
+        _is_qr_within_tol(z, q)
+        assert _replaced(z, q) == list(range(r, n))
+        lib, _ = np.linalg.qr(z[:, :r])
+        lib = lib * np.sign(np.diag(lib.T @ z[:, :r]))[None, :]
+        assert np.abs(q[:, :r] - lib).max() <= 1e-10
+        u = np.linalg.svd(z)[0]
+        comp = u[:, r:] @ u[:, r:].T
+        assert np.abs(q[:, r:] @ q[:, r:].T - comp).max() <= 1e-10
+    # nothing to span: every column is completed, and the basis is orthonormal
+    q0 = S.qr_gs(np.zeros((4, 4)))
+    _is_qr_within_tol(np.zeros((4, 4)), q0)
+
+
+def test_gram_schmidt_with_dependent_middle_columns_is_a_qr_within_tolerance():
+    """A zero column first, a copy of an earlier column in the middle and a
+    near-copy (within 1e-7 of it) further on: the result is still a QR of a
+    matrix within tol of z, column by column, and z's range lies in the span
+    of the columns that were not completed plus those completed before the
+    last new direction."""
+    rng = np.random.default_rng(17)
+    n = 8
+    z = rng.normal(size=(n, n))
+    z[:, 0] = 0.0
+    z[:, 3] = z[:, 1]
+    z[:, 6] = 2.0 * z[:, 2] + 1e-7 * rng.normal(size=n)
+    q = S.qr_gs(z)
+    _is_qr_within_tol(z, q)
+    rep = _replaced(z, q)
+    assert rep[:2] == [0, 3] and 6 in rep
+    u, s, _ = np.linalg.svd(z)
+    rk = int(np.sum(s > 1e-6 * s[0]))
+    assert n - rk <= len(rep)
+
+
+def test_refresh_of_rank_deficient_soap_factors():
+    """The refreshes of an 11-step oracle run (64x128, first refresh at the
+    tenth update) include rank-deficient factors: the ARM output layer's
+    input factor and the synthesis factors collect fewer gradient directions
+    than their size.  For every refresh input z = P Q_sorted: the result is a
+    QR of z within tol; its columns up to the first completed one equal the
+    Householder QR of the same columns; every completed column is orthogonal
+    to z's range within tol of |z|."""
+    calls = []
+    orig = S.qr_gs
+
+    def spy(z, tol=S.QR_TOL):
+        q = orig(z, tol)
+        calls.append((z.copy(), q.copy()))
+        return q
+
+    mc = wl.config_hop()
+    H, W, seed = 64, 128, 31
+    ora = R.OracleState(mc.as_dict(), H, W, wl.synth_image(H, W, seed), 1e-3, seed,
+                        wl.random_latents(mc, H, W, seed, scale=1.5),
+                        wl.init_params(mc, seed, arm_out_zero=False), optimizer="soap")
+    S.qr_gs = spy
+    try:
+        for t in range(1, 12):
+            ora.step(t, *R.schedule(t, 200))
+    finally:
+        S.qr_gs = orig
+    assert ora.soap.s == 10 and calls
+    n_completed = 0
+    for z, q in calls:
+        _is_qr_within_tol(z, q)
+        rep = _replaced(z, q)
+        k0 = rep[0] if rep else z.shape[1]
+        lib, _ = np.linalg.qr(z[:, :k0])
+        lib = lib * np.sign(np.diag(lib.T @ z[:, :k0]))[None, :]
+        assert np.abs(q[:, :k0] - lib).max() <= 1e-9
+        zn = np.linalg.norm(z, 2)
+        for k in rep:
+            assert np.linalg.norm(z.T @ q[:, k]) <= S.QR_TOL * zn
+        n_completed += len(rep)
+    assert n_completed >= 10
