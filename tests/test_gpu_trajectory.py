@@ -43,7 +43,7 @@ GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                     "trajectory_512x768_1000.json")
 # (synthesis-adjoint chunks per workgroup, residual-adjoint tiles per
 # workgroup): 0 keeps the default
-SHAPES = [(0, 0), (6, 1), (24, 1), (12, 4)]
+SHAPES = [(0, 0), (6, 1), (24, 1), (9, 2)]
 
 
 def _j(r, hw):
