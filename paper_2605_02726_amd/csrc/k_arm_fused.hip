@@ -18,13 +18,16 @@
 // segments of 128 columns; wavefront w owns columns [32 w, 32 w + 32) of the
 // segment in both rows.  The quantised latents of the band and its causal
 // halo (4 rows above, 4 columns each side) are staged in LDS.  The context
-// gradient is scattered into an LDS accumulator covering the band plus that
-// halo, in a fixed order (even wavefronts, then odd ones; within a
-// wavefront, lanes 0-31 then 32-63), so the result is deterministic; each
-// band writes its own rows to plane A and the 4 halo rows above it to planes
-// B1 and B2 (for the bands one and two above).  Weight gradients stay in MFMA accumulators across the
-// band and are reduced over the 8 wavefronts in a fixed order into one
-// partial row per workgroup.
+// gradient goes to the neighbours without atomics: a wavefront stages its
+// tile's slot gradients in LDS and each lane gathers, for one destination
+// column, the slots that reach it (fixed slot order), adding the sums to the
+// wavefront's private window over the band rows plus that halo; the
+// windows are merged in wavefront order at the end of each segment, so the
+// result is deterministic.  Each band writes its own rows to plane A and
+// the 4 halo rows above it to planes B1 and B2 (for the bands one and two
+// above).  Weight gradients stay in MFMA accumulators across the band and
+// are reduced over the 4 wavefronts in a fixed order into one partial row
+// per band.
 #include "cc_internal.h"
 
 #include <math.h>
@@ -41,6 +44,7 @@ constexpr int NW = 4;              // wavefronts per workgroup
 constexpr int SW = 32 * NW;        // segment width
 constexpr int WR = SW + 2 * HALO;  // LDS row: segment plus the halo columns
 constexpr int PW = 32 + 2 * HALO;  // private accumulator row of one wavefront
+constexpr int GP = 32 + 4 * HALO;  // staged slot-gradient row (positions -8 .. 39)
 
 // The first 24 causal neighbours in decoding order (half-plane {dy < 0, or
 // dy = 0 and dx < 0} sorted by (dy^2 + dx^2, dy, dx)), as LDS offsets within
@@ -52,7 +56,6 @@ constexpr int CDY[NOFF] = {-1, 0, -1, -1, -2, 0, -2, -2, -1, -1, -2, -2,
 constexpr int CDX[NOFF] = {0, -1, -1, 1, 0, -2, -1, 1, -2, 2, -2, 2,
                            0, -3, -1, 1, -3, 3, -2, 2, -3, 3, 0, -4};
 __host__ __device__ constexpr int coff(int m) { return m < NOFF ? CDY[m] * WR + CDX[m] : 0; }
-__host__ __device__ constexpr int poff(int m) { return m < NOFF ? CDY[m] * PW + CDX[m] : 0; }
 
 __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -163,6 +166,9 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
   // the next segment
   __shared__ float pacc[NW][HALO + TH][PW];
   __shared__ float cin[HALO + TH][2 * HALO], cout[HALO + TH][2 * HALO];
+  // per-wavefront staging of one tile's slot gradients for the gather:
+  // [slot][position + 2 HALO], rows 0-31 the MFMA rows, row 32 the direct term
+  __shared__ float gsc[NW][33][GP];
   // end-of-band weight-gradient sums of the four accumulators (the weights
   // are staged through the same storage at the start)
   __shared__ float wsum_raw[4 * 32 * 33];
@@ -193,6 +199,7 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
     vec[4][m] = (stab && m < CTX) ? P[d->p_asw + m] : 0.0f;
     vec[5][m] = (stab && m < CTX) ? P[d->p_asw + CTX + m] : 0.0f;
   }
+  for (int i = tid; i < NW * 33 * GP; i += NW * 64) (&gsc[0][0][0])[i] = 0.0f;
   // A operands (weights, split BF16) per lane and K step, kept in LDS:
   // operand (matrix mat, step s) of lane l is wop[mat][s][l] (hi) and
   // wopl[mat][s][l] (lo).  W1 and W2 are first staged in FP32 through the
@@ -483,23 +490,29 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
         acc4 = mma_split(ah, al, xh, xl, acc4);
       }
 
-      // ---- scatter the context gradient (and the direct term) into this
-      // wavefront's window: half 0's lanes, then half 1's (one instruction
-      // never carries two additions to one address from the two halves)
-      if (valid) {
-        float* pw = &pacc[wave][HALO + r][HALO + n];
-        for (int half = 0; half < 2; ++half) {
-          if (hh == half) {
+      // ---- context gradient to the neighbours, without atomics: this
+      // wavefront stages the slot gradients as [slot][position] (the direct
+      // term as slot 32; positions padded with 2*HALO zeros on each side;
+      // outside the grid they are exactly zero), then each lane owns one
+      // destination column of the rows r - HALO .. r, sums the slots that
+      // reach it in slot order and adds the sums to its window
+      {
+        float* g = &gsc[wave][0][0] + (hh ? 4 * GP : 0) + 2 * HALO + n;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-              // slot of register i in this half: both candidates are
-              // compile-time constants, so no table is read at run time
-              const int m = half ? mrow(i, 1) : mrow(i, 0);
-              if (m < S) atomicAdd(pw + (half ? poff(mrow(i, 1)) : poff(mrow(i, 0))), dc[i]);
-            }
-            if (half == 0) atomicAdd(pw, gd * rs);
-          }
-        }
+        for (int i = 0; i < 16; ++i) g[mrow(i, 0) * GP] = dc[i];
+        if (hh == 0) gsc[wave][32][2 * HALO + n] = gd * rs;
+      }
+      if (lane < PW) {
+        const float* g = &gsc[wave][0][0] + lane + HALO;
+        float sr[HALO + 1];
+        sr[0] = g[32 * GP];
+#pragma unroll
+        for (int q = 1; q <= HALO; ++q) sr[q] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < S; ++m) sr[-CDY[m]] += g[m * GP - CDX[m]];
+        float* pw = &pacc[wave][HALO + r][lane];
+#pragma unroll
+        for (int q = 0; q <= HALO; ++q) pw[-q * PW] += sr[q];
       }
 
       transpose2(b1, pu, ah);                // dH1^T (+ stabilizer rows)
