@@ -87,6 +87,15 @@ struct Layout {
 
 // Workgroups of the IFCE gradient pooling: one per (child grid c, channel,
 // base block of side 2^(L-1-c)).
+// Producer rows of the ARM for the current form: the plain kernel's rows
+// cover the ARM and IFCE parameters; the fused kernel's rows end before the
+// IFCE parameters, whose gradients come from the pooling kernel's rows.
+void arm_form(DevDesc& h) {
+  h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
+  h.prod[h.prod_arm].nrows = h.arm_nwg;
+  h.prod[h.prod_arm].pcnt = (h.arm_fused && h.F > 0 && h.G > 0) ? h.p_iw[0] : h.n_arm_par;
+}
+
 int pool_blocks(const DevDesc& h) {
   int tot = 0;
   for (int c = 0; c < h.G; ++c) {
@@ -332,6 +341,16 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
   h.prod_arm = q;
   h.prod[q++] = {0, h.n_arm_par, h.arm_nwg, 0, wpo};
   wpo += (long long)std::max(h.arm_nwg_plain, h.arm_nwg_fused) * h.n_arm_par;
+  // the fused form takes the IFCE weight gradients of grid c from the pooling
+  // kernel: one partial row per pooling block (F (nin + 1) entries, the
+  // grid's IFCE weights then biases); its ARM rows stop before them
+  h.prod_ifce0 = q;
+  for (int c = 0; h.F > 0 && c < h.G; ++c) {
+    const int B = 1 << (h.L - 1 - c);
+    const int rows = (h.gh[c] / B) * (h.gw[c] / B), cnt = h.F * (h.nin[c] + 1);
+    h.prod[q++] = {h.p_iw[c], cnt, rows, 0, wpo};
+    wpo += (long long)rows * cnt;
+  }
   h.ups_jc = ups_chain_first(h);
   h.prod_ups1 = q;
   for (int j = 1; j < h.L; ++j) {
@@ -358,8 +377,7 @@ void build_layout(const cc_config* c, int H, int W, Layout& Lo) {
     wpo += (long long)res_tiles(h) * 84;
   }
   h.nprod = q;
-  h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
-  h.prod[h.prod_arm].nrows = h.arm_nwg;
+  arm_form(h);
   h.arm_wgs = arm_default_wgs(h);
   arm_pack(h, h.arm_wgs, Lo.arm_blist, Lo.arm_wbeg);
 
@@ -1631,8 +1649,7 @@ int cc_set_precision(cc_state* s, int precision) {
   DevDesc& h = s->lo.h;
   s->precision = precision;
   h.arm_fused = (precision == CC_BF16_FUSED && cc_arm_fused_supported(h)) ? 1 : 0;
-  h.arm_nwg = h.arm_fused ? h.arm_nwg_fused : h.arm_nwg_plain;
-  h.prod[h.prod_arm].nrows = h.arm_nwg;
+  arm_form(h);
   HIPCHK(hipMemcpy(s->ddev, &h, sizeof(DevDesc), hipMemcpyHostToDevice));
   return CC_OK;
 }

@@ -11,7 +11,7 @@
 #define CC_MAX_G 12   // grids of the flat latent pyramid (latent + hyperlatent)
 #define CC_MAX_NIN 10 // inputs of one IFCE (coarser latent grids + hyperlatent grids)
 #define CC_MAX_S 32
-#define CC_MAX_PROD 24
+#define CC_MAX_PROD 32
 #define CC_NOALLOC_SCRATCH_BYTES (64u << 20)  // static scratch of cc_rd_eval_noalloc, per device
 
 // One producer of weight-gradient partial rows (a kernel whose workgroups
@@ -61,6 +61,7 @@ struct DevDesc {
   int syn_cpw, res_tpw;         // synthesis chunks / residual tiles per workgroup (launch shape)
   ProdSeg prod[CC_MAX_PROD];
   int prod_arm, prod_syn, prod_res0, prod_ups1, prod_upc1;   // producer indices
+  int prod_ifce0;               // fused form: IFCE weight gradients of grid c from the pooling kernel
   // ---- buffers (device pointers inside the slab)
   float *img, *theta, *m, *v, *grad, *yhat, *dq, *dc, *df, *dyd, *dyq;
   float *U, *dU, *V, *dV, *X, *dXa, *dXb, *wp;

@@ -5,7 +5,7 @@
 // backward), with the three GEMM-shaped parts on the matrix cores:
 //   forward   H1 = relu(W1 C + b1), H2 = relu(W2 H1 + b2)
 //   backward  dH1 = W2^T dH2', dC = W1^T dH1'
-//   weights   dW1 = dH1' C^T, dW2 = dH2' H1^T, dW3/dWs/dW_ifce likewise
+//   weights   dW1 = dH1' C^T, dW2 = dH2' H1^T, dW3/dWs likewise
 // with latent positions on the N axis: 32 positions per MFMA, operands in
 // split BF16 (hi + lo), accumulation in FP32.  The output layer (2 units),
 // the stabilizer, the rate and its derivatives run in FP32 on the vector
@@ -169,11 +169,11 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
   // per-wavefront staging of one tile's slot gradients for the gather:
   // [slot][position + 2 HALO], rows 0-31 the MFMA rows, row 32 the direct term
   __shared__ float gsc[NW][33][GP];
-  // end-of-band weight-gradient sums of the four accumulators (the weights
+  // end-of-band weight-gradient sums of the three accumulators (the weights
   // are staged through the same storage at the start)
-  __shared__ float wsum_raw[4 * 32 * 33];
+  __shared__ float wsum_raw[3 * 32 * 33];
   float(*wsum)[32][33] = reinterpret_cast<float(*)[32][33]>(wsum_raw);
-  static_assert(H1 * CTX + H2 * H1 <= 4 * 32 * 33, "weight staging");
+  static_assert(H1 * CTX + H2 * H1 <= 3 * 32 * 33, "weight staging");
   __shared__ float pwin[CC_MAX_NIN][SW / 2 + 1];   // IFCE inputs of the segment
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
   __shared__ float iw[8][CC_MAX_NIN], ib[8];  // IFCE weights [feature][input] (zero padded), biases
@@ -284,10 +284,10 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
   // weight-gradient accumulators (rows x columns, positions summed):
   // acc1 = dH1 C^T (+ stabilizer rows H1, H1 + 1; bias column CTX),
   // acc2 = dH2 H1^T (bias column H1), acc3 = the same dH1 rows H1, H1 + 1
-  // (d mu, d l) against H2^T: the output layer (bias column H2),
-  // acc4 = dC (IFCE slots S + f) against the IFCE inputs (bias column
-  // CC_MAX_NIN)
-  f32x16 acc1 = {}, acc2 = {}, acc3 = {}, acc4 = {};
+  // (d mu, d l) against H2^T: the output layer (bias column H2).  The IFCE
+  // weight gradients come from the pooling of the per-position IFCE
+  // gradients written below (they multiply the pooled sums by the inputs).
+  f32x16 acc1 = {}, acc2 = {}, acc3 = {};
   double bsum = 0.0;
   for (int i = tid; i < NW * (HALO + TH) * PW; i += NW * 64) (&pacc[0][0][0])[i] = 0.0f;
   if (tid < (HALO + TH) * 2 * HALO) (&cin[0][0])[tid] = 0.0f;
@@ -462,33 +462,6 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
         }
       }
 
-      // ---- weight gradients, positions on K: every operand transposed
-      // through the matrix cores, hi and lo parts apart (exact)
-      bf16x8 ah[2], al[2], xh[2], xl[2];
-      if (has_ifce) {
-        bf16x8 ch[2], cl[2];
-        split8(dc, ch[0], cl[0]);
-        split8(dc + 8, ch[1], cl[1]);
-        transpose2(ch, pu, ah);              // dC^T: rows S + f are the IFCE features
-        transpose2(cl, pu, al);
-        // K-step 0 carries input q = 8 hh + i (q < CC_MAX_NIN), step 1 nothing
-        float rq[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          float v = 0.0f;
-          if (i < 8) {
-            const float v1 = (8 + i < CC_MAX_NIN) ? r_in[(8 + i) % CC_MAX_NIN] : 0.0f;
-            v = hh ? v1 : r_in[i];
-          }
-          rq[i] = v;
-        }
-        split8(rq, ch[0], cl[0]);
-        split8(rq + 8, ch[1], cl[1]);
-        transpose2(ch, pc, xh);              // the inputs^T, ones in column CC_MAX_NIN
-        transpose2(cl, pc, xl);
-        if (n == CC_MAX_NIN) set_column(xh, xl, 1.0f);
-        acc4 = mma_split(ah, al, xh, xl, acc4);
-      }
 
       // ---- context gradient to the neighbours, without atomics: this
       // wavefront stages the slot gradients as [slot][position] (the direct
@@ -515,6 +488,9 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
         for (int q = 0; q <= HALO; ++q) pw[-q * PW] += sr[q];
       }
 
+      // ---- weight gradients, positions on K: every operand transposed
+      // through the matrix cores, hi and lo parts apart (exact)
+      bf16x8 ah[2], al[2], xh[2], xl[2];
       transpose2(b1, pu, ah);                // dH1^T (+ stabilizer rows)
       transpose2(b1l, pu, al);
       transpose2(bc, pc, xh);                // C^T, ones in column CTX
@@ -588,23 +564,22 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
           wsum[0][m][n] = acc1[i];
           wsum[1][m][n] = acc2[i];
           wsum[2][m][n] = acc3[i];
-          wsum[3][m][n] = acc4[i];
         } else {
           wsum[0][m][n] += acc1[i];
           wsum[1][m][n] += acc2[i];
           wsum[2][m][n] += acc3[i];
-          wsum[3][m][n] += acc4[i];
         }
       }
     }
     __syncthreads();
   }
-  float* out = d->wp + d->prod[d->prod_arm].off + (size_t)bidx * d->n_arm_par;
-  for (int p = tid; p < d->n_arm_par; p += NW * 64) {
+  // the ARM parameters only (the row ends before the IFCE parameters)
+  const int pcnt = d->prod[d->prod_arm].pcnt;
+  float* out = d->wp + d->prod[d->prod_arm].off + (size_t)bidx * pcnt;
+  for (int p = tid; p < pcnt; p += NW * 64) {
     const unsigned e = d->arm_ftab[p];
-    const int kr = (e >> 16) & 0xFF;
     const int a = (e >> 10) & 3, row = (e >> 5) & 31, col = e & 31;
-    out[p] = (kr == 0xFF || kr == k) ? wsum[a][row][col] : 0.0f;
+    out[p] = wsum[a][row][col];
   }
   }
   // LDS of this band (window, accumulators, sums, IFCE weights) is reused
@@ -633,7 +608,8 @@ int launch_t(const Launch& l, int bwd, hipStream_t st) {
 
 int cc_arm_fused_supported(const DevDesc& h) {
   if (h.S > NOFF) return 0;
-  // IFCE features in the rows S + f of the transposed context gradient
+  // the context (spatial slots and IFCE features) and its bias column fit
+  // one 32-row tile
   if (h.S + h.F > 31) return 0;
   for (int k = 0; k < h.G; ++k)
     if (h.nin[k] > CC_MAX_NIN) return 0;

@@ -149,6 +149,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_qtrain(Launch L, StepPack A) {
 __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
   __shared__ float buf[2][CC_POOL_BLOCK * CC_POOL_BLOCK / 4];
   __shared__ float base[CC_POOL_BLOCK * CC_POOL_BLOCK];
+  __shared__ float red[CC_MAX_NIN][CC_ELT_TILE / 64];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
   int b = blockIdx.x - L.tile0[im];
@@ -186,6 +187,17 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
     }
   }
   __syncthreads();
+  // fused form: the IFCE weight gradient of feature ch,
+  //   dW[ch][q] = sum over the grid's positions of df_ch * r_q,
+  // where input q is grid isrc[c][q] read at (y >> s, x >> s), s = ish[c][q],
+  // equals the sum over that input grid's positions of its value times the
+  // df sum pooled to shift s, which this block forms below; the bias
+  // gradient is the block's whole sum
+  const bool wgrad = d->arm_fused != 0;
+  const int nin = d->nin[c];
+  float acc[CC_MAX_NIN];
+#pragma unroll
+  for (int q = 0; q < CC_MAX_NIN; ++q) acc[q] = 0.0f;
   const float* in = base;
   int side = B;
   for (int f = 1; f <= d->L - 1 - c; ++f) {
@@ -199,10 +211,39 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
       const float v = (r0[0] + r0[1]) + (r0[side] + r0[side + 1]);
       out[i] = v;
       dst[(by * so + y) * w + bx * so + x] = v;
+      if (wgrad) {
+#pragma unroll
+        for (int q = 0; q < CC_MAX_NIN; ++q) {
+          if (q < nin && d->ish[c][q] == f) {
+            const int j = d->isrc[c][q];
+            acc[q] += v * d->yhat[d->goff[j] + (by * so + y) * d->gw[j] + bx * so + x];
+          }
+        }
+      }
     }
     __syncthreads();
     in = out;
     side = so;
+  }
+  if (!wgrad) return;
+  // fixed-order block sums: lanes (xor tree), then the waves in order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < CC_MAX_NIN; ++q) {
+    float v = acc[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[q][wv] = v;
+  }
+  __syncthreads();
+  const int pi = d->prod_ifce0 + c;
+  float* row = d->wp + d->prod[pi].off + (size_t)(by * tx + bx) * d->prod[pi].pcnt;
+  if (threadIdx.x < nin) {
+    float s = 0.0f;
+    for (int u = 0; u < CC_ELT_TILE / 64; ++u) s += red[threadIdx.x][u];
+    row[ch * nin + threadIdx.x] = s;
+  } else if (threadIdx.x == CC_MAX_NIN) {
+    // the last level holds one value: the block's sum of df_ch
+    row[d->F * nin + ch] = in[0];
   }
 }
 
