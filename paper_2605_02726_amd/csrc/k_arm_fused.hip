@@ -151,7 +151,7 @@ __device__ __forceinline__ void set_column(bf16x8* hi, bf16x8* lo, float v) {
 }
 
 template <int S, int F, int H1, int H2>
-__global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
+__global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   constexpr int CTX = S + F;
   static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 <= 32 && CC_MAX_NIN + 1 <= 32, "shape");
   // The linear stabilizer rides in the first layer's spare output rows H1,
@@ -333,6 +333,11 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
 #pragma unroll 1
     for (int r = 0; r < TH; ++r) {
       const int y = y0 + r, x = x0 + 32 * wave + n;
+      // an opaque zero added to the LDS indices of the weights and biases:
+      // they are read again every tile instead of being held in registers
+      // across the band, which keeps the kernel at two wavefronts per SIMD
+      int zq = 0;
+      __asm__ volatile("" : "+s"(zq));
       const bool valid = y < h && x < w;
       const int lc = HALO + 32 * wave + n;       // LDS column of this position
       // ---- context (FP32) in operand order: slot kk = 16 s + 8 hh + i
@@ -352,9 +357,9 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
             v = (&ywin[HALO + r][lc])[hh ? coff(k1) : coff(k0)];
           } else if (kk < CTX && has_ifce) {
             const int f = kk - S;
-            float a = ib[f];
+            float a = ib[f + zq];
 #pragma unroll
-            for (int q = 0; q < CC_MAX_NIN; ++q) a += iw[f][q] * r_in[q];
+            for (int q = 0; q < CC_MAX_NIN; ++q) a += iw[f][q + zq] * r_in[q];
             v = a;
           }
           cf[s][i] = v;
@@ -365,8 +370,8 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
       const bool do_bwd = bwd > 0;
       // ---- layer 1 (with the stabilizer in rows H1, H1 + 1) and 2
       f32x16 z = {};
-      f32x16 D = mfma3(wop[0][0][lane], wopl[0][0][lane], bc[0], bcl[0], z);
-      if (CTX > 16) D = mfma3(wop[0][1][lane], wopl[0][1][lane], bc[1], bcl[1], D);
+      f32x16 D = mfma3(wop[0][0][lane + zq], wopl[0][0][lane + zq], bc[0], bcl[0], z);
+      if (CTX > 16) D = mfma3(wop[0][1][lane + zq], wopl[0][1][lane + zq], bc[1], bcl[1], D);
       float o0 = hh == HS ? D[IS] : 0.0f, o1 = hh == HS ? D[IS + 1] : 0.0f;
       unsigned m1 = 0, m2 = 0;
       bf16x8 bh[2], bhl[2];
@@ -374,23 +379,23 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
         float hv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          hv[i] = fmaxf(D[i] + vec[0][mrow(i, hh)], 0.0f);
+          hv[i] = fmaxf(D[i] + vec[0][mrow(i, hh) + zq], 0.0f);
           m1 |= (hv[i] > 0.0f ? 1u : 0u) << i;
         }
         split8(hv, bh[0], bhl[0]);
         split8(hv + 8, bh[1], bhl[1]);
       }
-      D = mfma3(wop[1][0][lane], wopl[1][0][lane], bh[0], bhl[0], z);
-      D = mfma3(wop[1][1][lane], wopl[1][1][lane], bh[1], bhl[1], D);
+      D = mfma3(wop[1][0][lane + zq], wopl[1][0][lane + zq], bh[0], bhl[0], z);
+      D = mfma3(wop[1][1][lane + zq], wopl[1][1][lane + zq], bh[1], bhl[1], D);
       bf16x8 vh[2], vl[2];   // H2 (split, for the output layer's weight gradient)
       {
         float v2[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const float v = fmaxf(D[i] + vec[1][mrow(i, hh)], 0.0f);
+          const float v = fmaxf(D[i] + vec[1][mrow(i, hh) + zq], 0.0f);
           m2 |= (v > 0.0f ? 1u : 0u) << i;
-          o0 += vec[2][mrow(i, hh)] * v;
-          o1 += vec[3][mrow(i, hh)] * v;
+          o0 += vec[2][mrow(i, hh) + zq] * v;
+          o1 += vec[3][mrow(i, hh) + zq] * v;
           v2[i] = v;
         }
         split8(v2, vh[0], vl[0]);
@@ -427,12 +432,12 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
         float gv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-          gv[i] = ((m2 >> i) & 1u) ? vec[2][mrow(i, hh)] * dmu + vec[3][mrow(i, hh)] * dl : 0.0f;
+          gv[i] = ((m2 >> i) & 1u) ? vec[2][mrow(i, hh) + zq] * dmu + vec[3][mrow(i, hh) + zq] * dl : 0.0f;
         split8(gv, b2[0], b2l[0]);
         split8(gv + 8, b2[1], b2l[1]);
       }
-      D = mfma3(wop[2][0][lane], wopl[2][0][lane], b2[0], b2l[0], z);
-      D = mfma3(wop[2][1][lane], wopl[2][1][lane], b2[1], b2l[1], D);
+      D = mfma3(wop[2][0][lane + zq], wopl[2][0][lane + zq], b2[0], b2l[0], z);
+      D = mfma3(wop[2][1][lane + zq], wopl[2][1][lane + zq], b2[1], b2l[1], D);
       bf16x8 b1[2], b1l[2];   // dH1 with (d mu, d l) in the stabilizer rows
       {
         float gv[16];
@@ -449,8 +454,8 @@ __global__ __launch_bounds__(256, 1) void k_arm_fused(Launch Lc, int bwd) {
         split8(gv, b1[0], b1l[0]);
         split8(gv + 8, b1[1], b1l[1]);
       }
-      D = mfma3(wop[3][0][lane], wopl[3][0][lane], b1[0], b1l[0], z);
-      D = mfma3(wop[3][1][lane], wopl[3][1][lane], b1[1], b1l[1], D);
+      D = mfma3(wop[3][0][lane + zq], wopl[3][0][lane + zq], b1[0], b1l[0], z);
+      D = mfma3(wop[3][1][lane + zq], wopl[3][1][lane + zq], b1[1], b1l[1], D);
       float dc[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) dc[i] = D[i];
