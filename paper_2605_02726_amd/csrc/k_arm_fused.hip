@@ -175,6 +175,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   float(*wsum)[32][33] = reinterpret_cast<float(*)[32][33]>(wsum_raw);
   static_assert(H1 * CTX + H2 * H1 <= 3 * 32 * 33, "weight staging");
   __shared__ float pwin[CC_MAX_NIN][SW / 2 + 1];   // IFCE inputs of the segment
+  __shared__ float fwin[8][SW / 2];                 // IFCE features per column pair
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
   __shared__ float iw[8][CC_MAX_NIN], ib[8];  // IFCE weights [feature][input] (zero padded), biases
   __shared__ double bsh[NW];
@@ -276,10 +277,6 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
     iw[f][q] = (has_ifce && f < F && q < nin) ? P[d->p_iw[k] + f * nin + q] : 0.0f;
     if (q == 0) ib[f] = (has_ifce && f < F) ? P[d->p_ib[k] + f] : 0.0f;
   }
-  // resolution shift of every IFCE input (uniform)
-  int shq[CC_MAX_NIN];
-#pragma unroll
-  for (int q = 0; q < CC_MAX_NIN; ++q) shq[q] = q < nin ? d->ish[k][q] : 1;
 
   // weight-gradient accumulators (rows x columns, positions summed):
   // acc1 = dH1 C^T (+ stabilizer rows H1, H1 + 1; bias column CTX),
@@ -308,7 +305,27 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       yv[u] = (i < (HALO + TH) * WR && gy >= 0 && gy < h && gx >= 0 && gx < w) ? yg[gy * w + gx] : 0.0f;
     }
   };
+  // IFCE inputs of the segment: every input grid is coarser (shift >= 1)
+  // and y0 is even, so both rows share each input row; prefetched into
+  // registers with the window
+  constexpr int NQ = (CC_MAX_NIN * (SW / 2 + 1) + NW * 64 - 1) / (NW * 64);
+  float pv[NQ];
+  auto load_inputs = [&](int xs) {
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int i = tid + NW * 64 * u;
+      const int q = i / (SW / 2 + 1), c = i - q * (SW / 2 + 1);
+      float v = 0.0f;
+      if (q < nin) {
+        const int j = d->isrc[k][q], sh = d->ish[k][q];
+        const int py = y0 >> sh, px = (xs >> sh) + c;
+        if (py < d->gh[j] && px < d->gw[j]) v = d->yhat[d->goff[j] + py * d->gw[j] + px];
+      }
+      pv[u] = v;
+    }
+  };
   load_window(0);
+  if (has_ifce) load_inputs(0);
   for (int seg = 0; seg < nseg; ++seg) {
     const int x0 = seg * SW;
 #pragma unroll
@@ -316,16 +333,24 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       const int i = tid + NW * 64 * u;
       if (i < (HALO + TH) * WR) (&ywin[0][0])[i] = yv[u];
     }
-    // IFCE inputs of the band: every input grid is coarser (shift >= 1)
-    // and y0 is even, so both rows share each input row
     if (has_ifce) {
-      for (int i = tid; i < CC_MAX_NIN * (SW / 2 + 1); i += NW * 64) {
-        const int q = i / (SW / 2 + 1), c = i - q * (SW / 2 + 1);
-        if (q < nin) {
-          const int j = d->isrc[k][q], sh = d->ish[k][q];
-          const int py = y0 >> sh, px = (x0 >> sh) + c;
-          pwin[q][c] = (py < d->gh[j] && px < d->gw[j]) ? d->yhat[d->goff[j] + py * d->gw[j] + px] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        const int i = tid + NW * 64 * u;
+        if (i < CC_MAX_NIN * (SW / 2 + 1)) (&pwin[0][0])[i] = pv[u];
+      }
+      __syncthreads();
+      // IFCE features, once per column pair (the inputs are constant over
+      // each 2 x 2 block of the band): f = b + W r, inputs in order
+      for (int i = tid; i < F * (SW / 2); i += NW * 64) {
+        const int f = i / (SW / 2), c2 = i - f * (SW / 2);
+        const int xp = x0 + 2 * c2;
+        float a = ib[f];
+        for (int q = 0; q < nin; ++q) {
+          const int sh = d->ish[k][q];
+          a += iw[f][q] * pwin[q][(xp >> sh) - (x0 >> sh)];
         }
+        fwin[f][c2] = a;
       }
     }
     __syncthreads();
@@ -341,10 +366,6 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       const bool valid = y < h && x < w;
       const int lc = HALO + 32 * wave + n;       // LDS column of this position
       // ---- context (FP32) in operand order: slot kk = 16 s + 8 hh + i
-      float r_in[CC_MAX_NIN];
-#pragma unroll
-      for (int q = 0; q < CC_MAX_NIN; ++q)
-        r_in[q] = (has_ifce && q < nin) ? pwin[q][(x >> shq[q]) - (x0 >> shq[q])] : 0.0f;
       float cf[2][8];
 #pragma unroll
       for (int s = 0; s < 2; ++s)
@@ -356,11 +377,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
           if (kk < S) {
             v = (&ywin[HALO + r][lc])[hh ? coff(k1) : coff(k0)];
           } else if (kk < CTX && has_ifce) {
-            const int f = kk - S;
-            float a = ib[f + zq];
-#pragma unroll
-            for (int q = 0; q < CC_MAX_NIN; ++q) a += iw[f][q + zq] * r_in[q];
-            v = a;
+            v = fwin[kk - S][(32 * wave + n) >> 1];
           }
           cf[s][i] = v;
         }
@@ -514,7 +531,10 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       acc2 = mma_split(ah, al, xh, xl, acc2);
     }
     __syncthreads();
-    if (seg + 1 < nseg) load_window(x0 + SW);   // in flight during the merge
+    if (seg + 1 < nseg) {   // in flight during the merge
+      load_window(x0 + SW);
+      if (has_ifce) load_inputs(x0 + SW);
+    }
     // ---- merge the wavefront windows (fixed order) with the carried
     // columns, write the finished columns of this segment and carry the last
     // 2*HALO columns into the next one.  Row rr of the window is grid row
