@@ -176,6 +176,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   static_assert(H1 * CTX + H2 * H1 <= 3 * 32 * 33, "weight staging");
   __shared__ float pwin[CC_MAX_NIN][SW / 2 + 1];   // IFCE inputs of the segment
   __shared__ float fwin[8][SW / 2];                 // IFCE features per column pair
+  __shared__ float dfs[NW][8][32];                  // top-row pair sums of the IFCE gradients
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
   __shared__ float iw[8][CC_MAX_NIN], ib[8];  // IFCE weights [feature][input] (zero padded), biases
   __shared__ double bsh[NW];
@@ -476,11 +477,24 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       float dc[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) dc[i] = D[i];
-      if (has_ifce && valid) {
+      // IFCE gradients, summed over each 2 x 2 block (column pairs of both
+      // band rows, in the order (top pair) + (bottom pair)) and written at
+      // the next coarser resolution: the first level of the IFCE pooling
+      // (the per-position values are not needed; grids with IFCEs have even
+      // sides, and outside the grid the gradients are exactly zero)
+      if (has_ifce) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int m = mrow(i, hh);
-          if (m >= S && m < CTX) d->df[d->dfoff[k][0] + (m - S) * nk + y * w + x] = dc[i];
+          if (m >= S && m < CTX) {
+            const float pr = dc[i] + __shfl_xor(dc[i], 1);
+            if (r == 0) {
+              dfs[wave][m - S][n] = pr;
+            } else if ((n & 1) == 0 && x < w) {
+              const int w1 = d->gw[k + 1], n1 = d->gh[k + 1] * w1;
+              d->df[d->dfoff[k][1] + (m - S) * n1 + (y0 >> 1) * w1 + (x >> 1)] = dfs[wave][m - S][n] + pr;
+            }
+          }
         }
       }
 

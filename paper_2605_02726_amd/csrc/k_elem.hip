@@ -165,24 +165,28 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
   const int tx = d->gw[c] / B, ty = d->gh[c] / B;
   const int ch = b / (tx * ty), t = b - ch * (tx * ty);
   const int by = t / tx, bx = t - by * tx;
+  // the plain ARM kernel writes the per-position gradients (level 0); the
+  // fused one writes them already summed over 2 x 2 blocks (level 1)
+  const int l0 = d->arm_fused ? 1 : 0;
+  const int Bb = B >> l0;
   {
-    const int w0 = d->gw[c], n0 = d->gh[c] * w0;
-    const float* src = d->df + d->dfoff[c][0] + (size_t)ch * n0;
+    const int w0 = d->gw[c + l0], n0 = d->gh[c + l0] * w0;
+    const float* src = d->df + d->dfoff[c][l0] + (size_t)ch * n0;
     // loads in groups of 8 per thread, each group issued before its LDS
     // stores, so their latencies overlap
     constexpr int NB = 8;
-    for (int i0 = 0; i0 < B * B; i0 += NB * CC_ELT_TILE) {
+    for (int i0 = 0; i0 < Bb * Bb; i0 += NB * CC_ELT_TILE) {
       float v[NB];
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int i = i0 + u * CC_ELT_TILE + threadIdx.x;
-        const int y = i / B, x = i - y * B;
-        v[u] = i < B * B ? src[(by * B + y) * w0 + bx * B + x] : 0.0f;
+        const int y = i / Bb, x = i - y * Bb;
+        v[u] = i < Bb * Bb ? src[(by * Bb + y) * w0 + bx * Bb + x] : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < NB; ++u) {
         const int i = i0 + u * CC_ELT_TILE + threadIdx.x;
-        if (i < B * B) base[i] = v[u];
+        if (i < Bb * Bb) base[i] = v[u];
       }
     }
   }
@@ -198,9 +202,21 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
   float acc[CC_MAX_NIN];
 #pragma unroll
   for (int q = 0; q < CC_MAX_NIN; ++q) acc[q] = 0.0f;
+  auto wgrad_level = [&](int f, int so, int i, float v) {
+    const int y = i / so, x = i - y * so;
+#pragma unroll
+    for (int q = 0; q < CC_MAX_NIN; ++q) {
+      if (q < nin && d->ish[c][q] == f) {
+        const int j = d->isrc[c][q];
+        acc[q] += v * d->yhat[d->goff[j] + (by * so + y) * d->gw[j] + bx * so + x];
+      }
+    }
+  };
+  if (wgrad && l0 > 0)
+    for (int i = threadIdx.x; i < Bb * Bb; i += CC_ELT_TILE) wgrad_level(l0, Bb, i, base[i]);
   const float* in = base;
-  int side = B;
-  for (int f = 1; f <= d->L - 1 - c; ++f) {
+  int side = Bb;
+  for (int f = l0 + 1; f <= d->L - 1 - c; ++f) {
     const int so = side >> 1;
     float* out = buf[f & 1];
     const int w = d->gw[c + f], n = d->gh[c + f] * w;
@@ -211,15 +227,7 @@ __global__ __launch_bounds__(CC_ELT_TILE) void k_pool(Launch L) {
       const float v = (r0[0] + r0[1]) + (r0[side] + r0[side + 1]);
       out[i] = v;
       dst[(by * so + y) * w + bx * so + x] = v;
-      if (wgrad) {
-#pragma unroll
-        for (int q = 0; q < CC_MAX_NIN; ++q) {
-          if (q < nin && d->ish[c][q] == f) {
-            const int j = d->isrc[c][q];
-            acc[q] += v * d->yhat[d->goff[j] + (by * so + y) * d->gw[j] + bx * so + x];
-          }
-        }
-      }
+      if (wgrad) wgrad_level(f, so, i, v);
     }
     __syncthreads();
     in = out;
