@@ -273,8 +273,12 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   const bool has_ifce = F > 0 && k < d->G;
   const int nin = has_ifce ? d->nin[k] : 0;
   const float* yg = d->yhat + d->goff[k];
-  if (tid < 8 * CC_MAX_NIN) {
-    const int f = tid / CC_MAX_NIN, q = tid - f * CC_MAX_NIN;
+  // per-thread indices of the band-level code are recomputed from an opaque
+  // copy of the thread index rather than kept in registers across the band
+  int tb = threadIdx.x;
+  __asm__ volatile("" : "+v"(tb));
+  if (tb < 8 * CC_MAX_NIN) {
+    const int f = tb / CC_MAX_NIN, q = tb - f * CC_MAX_NIN;
     iw[f][q] = (has_ifce && f < F && q < nin) ? P[d->p_iw[k] + f * nin + q] : 0.0f;
     if (q == 0) ib[f] = (has_ifce && f < F) ? P[d->p_ib[k] + f] : 0.0f;
   }
@@ -287,8 +291,8 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   // gradients written below (they multiply the pooled sums by the inputs).
   f32x16 acc1 = {}, acc2 = {}, acc3 = {};
   double bsum = 0.0;
-  for (int i = tid; i < NW * (HALO + TH) * PW; i += NW * 64) (&pacc[0][0][0])[i] = 0.0f;
-  if (tid < (HALO + TH) * 2 * HALO) (&cin[0][0])[tid] = 0.0f;
+  for (int i = tb; i < NW * (HALO + TH) * PW; i += NW * 64) (&pacc[0][0][0])[i] = 0.0f;
+  if (tb < (HALO + TH) * 2 * HALO) (&cin[0][0])[tb] = 0.0f;
 
   const int nseg = (w + SW - 1) / SW;
   // latent window of a segment: rows y0-4 .. y0+TH-1, columns x0-4 ..
@@ -297,10 +301,10 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   // loaded while the current one's context gradients are merged
   constexpr int NY = ((HALO + TH) * WR + NW * 64 - 1) / (NW * 64);
   float yv[NY];
-  auto load_window = [&](int xs) {
+  auto load_window = [&](int xs, int t0) {
 #pragma unroll
     for (int u = 0; u < NY; ++u) {
-      const int i = tid + NW * 64 * u;
+      const int i = t0 + NW * 64 * u;
       const int r = i / WR, c = i - r * WR;
       const int gy = y0 - HALO + r, gx = xs - HALO + c;
       yv[u] = (i < (HALO + TH) * WR && gy >= 0 && gy < h && gx >= 0 && gx < w) ? yg[gy * w + gx] : 0.0f;
@@ -311,10 +315,10 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   // registers with the window
   constexpr int NQ = (CC_MAX_NIN * (SW / 2 + 1) + NW * 64 - 1) / (NW * 64);
   float pv[NQ];
-  auto load_inputs = [&](int xs) {
+  auto load_inputs = [&](int xs, int t0) {
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
-      const int i = tid + NW * 64 * u;
+      const int i = t0 + NW * 64 * u;
       const int q = i / (SW / 2 + 1), c = i - q * (SW / 2 + 1);
       float v = 0.0f;
       if (q < nin) {
@@ -325,25 +329,27 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
       pv[u] = v;
     }
   };
-  load_window(0);
-  if (has_ifce) load_inputs(0);
+  load_window(0, tb);
+  if (has_ifce) load_inputs(0, tb);
   for (int seg = 0; seg < nseg; ++seg) {
     const int x0 = seg * SW;
+    int tq = threadIdx.x;   // opaque copy, as for the band-level code
+    __asm__ volatile("" : "+v"(tq));
 #pragma unroll
     for (int u = 0; u < NY; ++u) {
-      const int i = tid + NW * 64 * u;
+      const int i = tq + NW * 64 * u;
       if (i < (HALO + TH) * WR) (&ywin[0][0])[i] = yv[u];
     }
     if (has_ifce) {
 #pragma unroll
       for (int u = 0; u < NQ; ++u) {
-        const int i = tid + NW * 64 * u;
+        const int i = tq + NW * 64 * u;
         if (i < CC_MAX_NIN * (SW / 2 + 1)) (&pwin[0][0])[i] = pv[u];
       }
       __syncthreads();
       // IFCE features, once per column pair (the inputs are constant over
       // each 2 x 2 block of the band): f = b + W r, inputs in order
-      for (int i = tid; i < F * (SW / 2); i += NW * 64) {
+      for (int i = tq; i < F * (SW / 2); i += NW * 64) {
         const int f = i / (SW / 2), c2 = i - f * (SW / 2);
         const int xp = x0 + 2 * c2;
         float a = ib[f];
@@ -546,8 +552,8 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
     }
     __syncthreads();
     if (seg + 1 < nseg) {   // in flight during the merge
-      load_window(x0 + SW);
-      if (has_ifce) load_inputs(x0 + SW);
+      load_window(x0 + SW, tq);
+      if (has_ifce) load_inputs(x0 + SW, tq);
     }
     // ---- merge the wavefront windows (fixed order) with the carried
     // columns, write the finished columns of this segment and carry the last
@@ -557,7 +563,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
     // the band two above (plane B2).
     if (bwd > 0) {
       const bool last = seg == nseg - 1;
-      for (int i = tid; i < (HALO + TH) * WR; i += NW * 64) {
+      for (int i = tq; i < (HALO + TH) * WR; i += NW * 64) {
         const int rr = i / WR, c = i - rr * WR;
         float v = c < 2 * HALO ? cin[rr][c] : 0.0f;
 #pragma unroll
@@ -578,7 +584,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
         d->dc[(size_t)plane * d->n_lat + d->goff[k] + gy * w + gx] = v;
       }
       __syncthreads();
-      if (tid < (HALO + TH) * 2 * HALO) (&cin[0][0])[tid] = (&cout[0][0])[tid];
+      if (tq < (HALO + TH) * 2 * HALO) (&cin[0][0])[tq] = (&cout[0][0])[tq];
     }
   }
 
@@ -615,7 +621,9 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   // the ARM parameters only (the row ends before the IFCE parameters)
   const int pcnt = d->prod[d->prod_arm].pcnt;
   float* out = d->wp + d->prod[d->prod_arm].off + (size_t)bidx * pcnt;
-  for (int p = tid; p < pcnt; p += NW * 64) {
+  int te = threadIdx.x;
+  __asm__ volatile("" : "+v"(te));
+  for (int p = te; p < pcnt; p += NW * 64) {
     const unsigned e = d->arm_ftab[p];
     const int a = (e >> 10) & 3, row = (e >> 5) & 31, col = e & 31;
     out[p] = wsum[a][row][col];
