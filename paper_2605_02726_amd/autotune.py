@@ -28,7 +28,7 @@ from .encoder import Encoder, schedule
 
 SYN_CHUNKS = (6, 8, 12, 16, 24)
 RES_TILES = (1, 2, 4)
-ARM_FRACTIONS = (1.0, 0.85, 0.7)   # of the library's packed default; one band per workgroup too
+ARM_FRACTIONS = (1.0, 0.85, 0.7, 0.6, 0.5)   # of the library's packed default; one band per workgroup too
 
 
 def size_bucket(H: int, W: int) -> str:
