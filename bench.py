@@ -522,6 +522,15 @@ def main():
             roof["kernel_alone"] = {"achieved": round(a1, 3), "frac": round(a1 / peak, 5),
                                     "avg_launch_ms": round(serial["arm_avg_ms"], 4),
                                     "note": "branches in order on one stream"}
+        if head == "bf16" and not args.no_kernel_timing:
+            # the tuner gives the ARM fewer workgroups than bands so that the
+            # overlapped distortion branch keeps part of every compute unit;
+            # alone on the chip it is fastest with one band per workgroup
+            ms_band = measure_kernel("bf16", "arm", steps=30, warmup=5)
+            a2 = flops / (ms_band / 1e3) / 1e12
+            roof["kernel_alone_one_band_per_workgroup"] = {
+                "achieved": round(a2, 3), "frac": round(a2 / peak, 5), "avg_launch_ms": round(ms_band, 4),
+                "note": "library default launch shape, branches in order"}
         if "fp32" in forms and "arm_avg_ms" in forms["fp32"]:
             a32 = flops / (forms["fp32"]["arm_avg_ms"] / 1e3) / 1e12
             roof["fp32_plain_kernel"] = {"bound": "alu", "achieved": round(a32, 3),
