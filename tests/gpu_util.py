@@ -62,49 +62,49 @@ def outlier_indices(a, b, rtol, segs):
     return np.concatenate(bad) if bad else np.zeros(0, np.int64)
 
 
-def unexplained_outliers(mc, H, W, bad, sites):
-    """Outlier elements that no near-threshold decision can reach.
-
-    Footprints on the latent grids (conservative rectangles):
+def footprint_rects(mc, H, W, site):
+    """Conservative footprint of one near-threshold decision on the latent
+    grids, as rectangles (grid, y0, y1, x0, x1), bounds inclusive:
       ARM ReLU, log-scale clamp, probability floor at grid k, position (y, x):
         grid k rows y-4..y, columns x-4..x+4 (the position and every causal
         neighbour its context reads), and the IFCE parents
         (y >> (j-k), x >> (j-k)) on the coarser grids j;
       synthesis ReLU at pixel (y, x): grid 0 at (y, x) +-1 and grid j >= 1
         within +-4 of (y >> j, x >> j) (j stride-2 upsamplings, each reading
-        inputs within +-2 of half its output index, add up to less than 4).
-    Decoder-parameter elements are never explained (every decision reaches
-    them, so they are held to the plain rule).  Returns the indices of `bad`
-    that lie in no footprint."""
+        inputs within +-2 of half its output index, add up to less than 4)."""
     L = mc.L
     levels = wl.grid_levels(mc)
+    _, tag, idx = site
+    rects = []
+    if tag[0] == "syn":
+        p = idx // mc.syn_hidden[tag[1]]
+        y, x = divmod(p, W)
+        rects.append((0, y - 1, y + 1, x - 1, x + 1))
+        for j in range(1, L):
+            rects.append((j, (y >> j) - 4, (y >> j) + 4, (x >> j) - 4, (x >> j) + 4))
+        return rects
+    k = tag[1]
+    pos = idx // mc.arm_hidden[tag[2]] if tag[0] == "arm" else idx
+    y, x = divmod(pos, W >> levels[k])
+    rects.append((k, y - 4, y, x - 4, x + 4))
+    if k < mc.n_ifce_grids:
+        for j in range(k + 1, len(levels)):
+            f = levels[j] - k
+            rects.append((j, y >> f, y >> f, x >> f, x >> f))
+    return rects
+
+
+def unexplained_outliers(mc, H, W, bad, sites):
+    """Outlier elements that no near-threshold decision can reach (footprints
+    of footprint_rects).  Decoder-parameter elements are never explained
+    (every decision reaches them, so they are held to the plain rule).
+    Returns the indices of `bad` that lie in no footprint."""
+    levels = wl.grid_levels(mc)
     masks = [np.zeros((H >> lev, W >> lev), bool) for lev in levels]
-    widths = {}
-    for i, w in enumerate(mc.arm_hidden):
-        widths[("arm", i)] = w
-    for i, w in enumerate(mc.syn_hidden):
-        widths[("syn", i)] = w
-
-    def mark(k, y0, y1, x0, x1):
-        h, w = masks[k].shape
-        masks[k][max(y0, 0):min(y1, h - 1) + 1, max(x0, 0):min(x1, w - 1) + 1] = True
-
-    for _, tag, idx in sites:
-        if tag[0] == "syn":
-            p = idx // widths[("syn", tag[1])]
-            y, x = divmod(p, W)
-            mark(0, y - 1, y + 1, x - 1, x + 1)
-            for j in range(1, L):
-                mark(j, (y >> j) - 4, (y >> j) + 4, (x >> j) - 4, (x >> j) + 4)
-            continue
-        k = tag[1]
-        pos = idx // widths[("arm", tag[2])] if tag[0] == "arm" else idx
-        y, x = divmod(pos, W >> levels[k])
-        mark(k, y - 4, y, x - 4, x + 4)
-        if k < mc.n_ifce_grids:
-            for j in range(k + 1, len(levels)):
-                f = levels[j] - k
-                mark(j, y >> f, y >> f, x >> f, x >> f)
+    for site in sites:
+        for (k, y0, y1, x0, x1) in footprint_rects(mc, H, W, site):
+            h, w = masks[k].shape
+            masks[k][max(y0, 0):min(y1, h - 1) + 1, max(x0, 0):min(x1, w - 1) + 1] = True
     starts = np.cumsum([0] + [(H >> lev) * (W >> lev) for lev in levels])
     out = []
     for e in np.asarray(bad).tolist():
@@ -228,8 +228,17 @@ def _oracle_grad(mc, H, W, theta, img, lam, quant, T, sigma, seed, t, tau, flip,
     loss.backward()
     if totals is not None:
         totals.update(loss=float(loss), bits=float(bits), mse=float(mse))
-    if capture is not None:   # for param_flip_slack
-        capture.update(grids=[g.detach() for g in grids], z=x0.detach(), go=h.grad.detach())
+    if capture is not None:   # for param_flip_slack and latent_flip_slack
+        # d yhat / d y of every latent (elementwise; 1 for the hard rounding's
+        # straight-through derivative)
+        if quant == "soft":
+            yd = th[:n_lat].detach().clone().requires_grad_(True)
+            qs = [R.q_train(g, T, sigma, nz) for g, nz in zip(R.split_latents(cfg, H, W, yd), noise)]
+            sum(q.sum() for q in qs).backward()
+            dq = yd.grad.numpy().copy()
+        else:
+            dq = np.ones(n_lat)
+        capture.update(grids=[g.detach() for g in grids], z=x0.detach(), go=h.grad.detach(), dq=dq)
     return th.grad.numpy().copy(), sites
 
 
@@ -327,6 +336,159 @@ def param_flip_slack(mc, H, W, theta, lam, sites, cap):
         slack += np.abs(d)
     return slack
 
+
+
+def latent_flip_slack(mc, H, W, theta, lam, sites, cap, elems):
+    """Per-element bound of what near-threshold decisions can do to the
+    latent gradient, for the latent indices `elems` (the elements outside the
+    plain rule), without one full oracle run per decision.
+
+    ARM ReLU, log-scale clamp and probability-floor decisions at one latent
+    position change only that position's rate term, whose gradient with
+    respect to its inputs (the causal neighbours, the latent itself, the IFCE
+    inputs) is recomputed with the decision inverted and without: exact to
+    first order, times lambda / (H W) and d yhat / d y.  A synthesis ReLU at
+    pixel p changes the gradient at the trunk input z(p) by dz (recomputed the
+    same way); its share on a latent of grid c is bounded by |dz_c| times the
+    largest weight of one grid-c latent in one upsampled pixel (an impulse
+    through the oracle's upsampling, replicate edges included), times
+    d yhat / d y.  Returns a dict {element: slack}."""
+    cfg = mc.as_dict()
+    n_lat = wl.n_latents(mc, H, W)
+    P = {k: v.detach() for k, v in R.unpack_params(cfg, torch.tensor(np.asarray(theta[n_lat:], np.float64))).items()}
+    grids = cap["grids"]
+    dq = cap["dq"]
+    levels = wl.grid_levels(mc)
+    starts = np.cumsum([0] + [int(g.numel()) for g in grids])
+    offs = R.causal_offsets(mc.n_spatial)
+    F, G = mc.n_ifce_feat, mc.n_ifce_grids
+    nl = len(mc.arm_hidden) + 1
+    lmin, lmax, pmin = mc.logscale_min, mc.logscale_max, mc.p_min
+    scale = lam / (H * W)
+    want = set(int(e) for e in elems)
+    out = {e: 0.0 for e in want}
+
+    def where(e):
+        k = int(np.searchsorted(starts, e, side="right") - 1)
+        y, x = divmod(int(e - starts[k]), grids[k].shape[1])
+        return k, y, x
+
+    def in_footprint(site, e):
+        k, y, x = where(e)
+        return any(kk == k and y0 <= y <= y1 and x0 <= x <= x1
+                   for (kk, y0, y1, x0, x1) in footprint_rects(mc, H, W, site))
+
+    def arm_inputs_grad(k, pos, tag, u):
+        gk = grids[k]
+        h, w = gk.shape
+        y, x = divmod(pos, w)
+        idx, vals = [], []
+        for dy, dx in offs:
+            yy, xx = y + dy, x + dx
+            inside = 0 <= yy < h and 0 <= xx < w
+            idx.append(int(starts[k] + yy * w + xx) if inside else -1)
+            vals.append(float(gk[yy, xx]) if inside else 0.0)
+        ridx, rvals = [], []
+        if F and k < G:
+            for j in range(k + 1, len(grids)):
+                sh = levels[j] - levels[k]
+                yy, xx = y >> sh, x >> sh
+                ridx.append(int(starts[j] + yy * grids[j].shape[1] + xx))
+                rvals.append(float(grids[j][yy, xx]))
+        s_t = torch.tensor([vals], dtype=torch.float64, requires_grad=True)
+        own = torch.tensor([float(gk[y, x])], dtype=torch.float64, requires_grad=True)
+        r_t = torch.tensor([rvals], dtype=torch.float64, requires_grad=True) if ridx else None
+        c = s_t
+        if F:
+            f = (r_t @ P[f"ifce.{k}.w"].T + P[f"ifce.{k}.b"]) if r_t is not None else s_t.new_zeros(1, F)
+            c = torch.cat([s_t, f], dim=1)
+        v = c
+        for i in range(nl):
+            v = v @ P[f"arm.{i}.w"].T + P[f"arm.{i}.b"]
+            if i < nl - 1:
+                if tag == ("arm", k, i):
+                    vd = v.detach()
+                    m = torch.zeros_like(vd, dtype=torch.bool)
+                    m[0, u] = True
+                    v = torch.where(m, torch.where(vd > 0, v * 0.0, v), torch.relu(v))
+                else:
+                    v = torch.relu(v)
+        if mc.arm_stab:
+            v = v + c @ P["arm.stab.w"].T + P["arm.stab.b"]
+        mu, ls = v[:, 0], v[:, 1]
+        lcl = torch.clamp(ls, lmin, lmax)
+        if tag == ("clamp", k):
+            lsd = ls.detach()
+            lcl = torch.where((lsd >= lmin) & (lsd <= lmax), lcl.detach(), ls)
+        b = torch.exp(lcl)
+        p = R.laplace_cdf(own + 0.5, mu, b) - R.laplace_cdf(own - 0.5, mu, b)
+        pc = torch.clamp(p, min=pmin)
+        if tag == ("floor", k):
+            pc = torch.where(p.detach() >= pmin, pc.detach(), p)
+        term = scale * (-torch.log(pc) / R.LN2).sum()
+        leaves = [s_t, own] + ([r_t] if r_t is not None else [])
+        grads = torch.autograd.grad(term, leaves, allow_unused=True)
+        res = {}
+        for ids, gr in zip([idx, [int(starts[k] + pos)], ridx], grads):
+            if gr is None:
+                continue
+            for e, gv in zip(ids, gr.reshape(-1).tolist()):
+                if e >= 0:
+                    res[e] = res.get(e, 0.0) + gv
+        return res
+
+    def syn_dz(pix, tag, u):
+        z = cap["z"][pix:pix + 1].clone().requires_grad_(True)
+        v = z
+        ns = len(mc.syn_hidden) + 1
+        for i in range(ns):
+            v = v @ P[f"syn.{i}.w"].T + P[f"syn.{i}.b"]
+            if i < ns - 1:
+                if tag == ("syn", i):
+                    vd = v.detach()
+                    m = torch.zeros_like(vd, dtype=torch.bool)
+                    m[0, u] = True
+                    v = torch.where(m, torch.where(vd > 0, v * 0.0, v), torch.relu(v))
+                else:
+                    v = torch.relu(v)
+        if mc.syn_stab:
+            v = v + z @ P["syn.stab.w"].T + P["syn.stab.b"]
+        return torch.autograd.grad((v * cap["go"][pix:pix + 1]).sum(), z)[0].reshape(-1)
+
+    wmax = None
+    for site in sites:
+        _, tag, i = site
+        cover = [e for e in want if in_footprint(site, e)]
+        if not cover:
+            continue
+        if tag[0] == "syn":
+            if wmax is None:
+                # largest weight of one latent of grid c in one upsampled pixel,
+                # over impulses at a corner, an edge and the interior
+                # (the same taps on a small 256x256 pyramid: the weights do not
+                # depend on the image size)
+                wmax = np.zeros(mc.L)
+                hs = [(256 >> lev, 256 >> lev) for lev in levels]
+                for c in range(mc.L):
+                    for (yy, xx) in ((0, 0), (0, hs[c][1] // 2), (hs[c][0] // 2, hs[c][1] // 2)):
+                        imp = [torch.zeros(sh, dtype=torch.float64) for sh in hs]
+                        imp[c][yy, xx] = 1.0
+                        zc = R.upsample(cfg, P, imp)
+                        wmax[c] = max(wmax[c], float(zc[c].abs().max()))
+            pix, u = divmod(i, mc.syn_hidden[tag[1]])
+            d = (syn_dz(pix, tag, u) - syn_dz(pix, None, u)).abs().numpy()
+            for e in cover:
+                k, _, _ = where(e)
+                if k < mc.L:
+                    out[e] += float(d[k]) * wmax[k] * abs(float(dq[e]))
+            continue
+        k = tag[1]
+        pos, u = divmod(i, mc.arm_hidden[tag[2]]) if tag[0] == "arm" else (i, 0)
+        a = arm_inputs_grad(k, pos, tag, u)
+        b = arm_inputs_grad(k, pos, None, u)
+        for e in cover:
+            out[e] += abs(a.get(e, 0.0) - b.get(e, 0.0)) * abs(float(dq[e]))
+    return out
 
 def decision_slack(mc, H, W, theta, img, lam, quant, T=None, sigma=None, seed=0, t=1,
                    tau=3e-6, max_sites=48):

@@ -75,3 +75,43 @@ def test_param_flip_slack_is_each_flips_exact_parameter_change():
         assert err <= 1e-9 * scale
         checked += exact[~ups].max() > 1e-9 * scale
     assert checked >= 3
+
+
+def test_latent_flip_slack_bounds_each_flips_latent_change():
+    """For single inverted decisions of every kind, the latent-gradient slack
+    equals the full oracle's change of every latent-gradient element for ARM
+    decisions (the position's own rate term is the only one that moves) and
+    bounds it for synthesis ReLUs (first order through the largest upsampling
+    weight)."""
+    from gpu_util import latent_flip_slack
+    mc = wl.config_hop()
+    H, W, seed = 128, 192, 12
+    img = wl.synth_image(H, W, seed)
+    lat = wl.random_latents(mc, H, W, seed, scale=2.0)
+    par = wl.init_params(mc, seed, arm_out_zero=False)
+    theta = np.concatenate([lat, par]).astype(np.float64)
+    args = (mc, H, W, theta, img, 1e-3, "soft", 0.35, 0.22, seed, 1)
+    cap = {}
+    g0, sites = _oracle_grad(*args, 3e-3, set(), capture=cap)
+    n_lat = wl.n_latents(mc, H, W)
+    scale = np.abs(g0[:n_lat]).max()
+    picked = {}
+    for s in sorted(sites):
+        kind = s[1][:2] if s[1][0] == "arm" else s[1][:1]
+        picked.setdefault(kind, s)
+    checked = 0
+    for kind, site in picked.items():
+        g1, _ = _oracle_grad(*args, 3e-3, {(site[1], site[2])})
+        exact = np.abs(g1[:n_lat] - g0[:n_lat])
+        elems = np.nonzero(exact > 1e-12 * scale)[0]
+        est = latent_flip_slack(mc, H, W, theta, 1e-3, [site], cap, elems)
+        e_arr = np.array([est[int(e)] for e in elems]) if len(elems) else np.zeros(0)
+        x_arr = exact[elems]
+        print(kind, site[1], f"{len(elems)} elements moved, max change {x_arr.max() if len(elems) else 0:.3e}, "
+              f"max slack {e_arr.max() if len(elems) else 0:.3e}", flush=True)
+        if site[1][0] == "syn":
+            assert np.all(x_arr <= e_arr * (1 + 1e-3) + 1e-10 * scale)
+        else:
+            assert np.all(np.abs(x_arr - e_arr) <= 1e-9 * scale + 1e-6 * x_arr)
+        checked += len(elems) > 0
+    assert checked >= 3

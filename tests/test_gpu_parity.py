@@ -15,7 +15,7 @@ import torch
 from oracle import coolchic_ref as R
 from paper_2605_02726_amd import workloads as wl
 
-from gpu_util import (_oracle_grad, decision_slack, outlier_indices, outliers,
+from gpu_util import (_oracle_grad, decision_slack, latent_flip_slack, outlier_indices, outliers,
                       param_flip_slack, segments, slack_outliers, unexplained_outliers)
 
 pytestmark = pytest.mark.gpu
@@ -269,10 +269,12 @@ def test_largest_serving_image(precision):
     decisions sit within rounding of their thresholds, too many to recompute
     the whole oracle once per decision.  Every latent element outside the
     per-element rule must lie inside the footprint of such a decision
-    (`unexplained_outliers`; the footprints cover about 0.5% of grid 0), and
-    every decoder-parameter element must hold the rule plus the first-order
-    slack of those decisions (`param_flip_slack`: each decision's own term
-    recomputed with the decision inverted).  FP32: rtol 1e-5, decisions
+    (`unexplained_outliers`; the footprints cover about 0.5% of grid 0) and
+    hold the rule plus the first-order change those decisions can make to it
+    (`latent_flip_slack`: each ARM decision's rate term recomputed with the
+    decision inverted, synthesis ReLUs bounded through the largest upsampling
+    weight), and every decoder-parameter element must hold the rule plus the
+    first-order slack of those decisions (`param_flip_slack`).  FP32: rtol 1e-5, decisions
     within 3e-6 of the layer's rms; BF16: rtol 2e-2, decisions within 3e-5
     (the resolution of its split operands)."""
     mc = wl.config_hop()
@@ -303,8 +305,15 @@ def test_largest_serving_image(precision):
     segs = segments(mc, H, W)
     n_lat = enc.n_lat
     bad = outlier_indices(g, gref, rtol, segs)
-    left = unexplained_outliers(mc, H, W, bad[bad < n_lat], sites)
+    bad_lat = bad[bad < n_lat]
+    left = unexplained_outliers(mc, H, W, bad_lat, sites)
     slack = np.zeros(g.size)
+    # latents outside the rule: each must hold it plus the first-order change
+    # that the near-threshold decisions around it can make
+    for e, v in latent_flip_slack(mc, H, W, theta, lam, sites, cap, bad_lat).items():
+        slack[e] = v
+    lsegs = [sg for sg in segs if sg[1].start < n_lat]
+    n_lat_bad, lworst = slack_outliers(g, gref, slack, rtol, lsegs)
     psegs = [sg for sg in segs if sg[1].start >= n_lat]
     n_par_bad, worst = slack_outliers(g, gref, slack, rtol, psegs)
     if n_par_bad:   # only then are the decisions' parameter terms needed
@@ -312,7 +321,8 @@ def test_largest_serving_image(precision):
         n_par_bad, worst = slack_outliers(g, gref, slack, rtol, psegs)
     print(f"[2048x2048/{precision}] {len(bad)} of {g.size} elements outside the rule, "
           f"{len(sites)} near-threshold decisions; latents outside every footprint: "
-          f"{len(left)} {left[:8]}; parameters outside rule + slack: {n_par_bad} {worst}",
-          flush=True)
+          f"{len(left)} {left[:8]}; latents outside rule + slack: {n_lat_bad} {lworst}; "
+          f"parameters outside rule + slack: {n_par_bad} {worst}", flush=True)
     assert not left
+    assert n_lat_bad == 0
     assert n_par_bad == 0
