@@ -172,11 +172,17 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_RES_TPW_MAX 16   // residual adjoint: largest tunable tiles per workgroup
 #define CC_PIX_TILE 256     // per-pixel kernels (res conv, ups): threads per block
 #define CC_WRED_SPLIT 32    // weight-gradient reduction: row splits of pass 1
-#define CC_FUSED_BAND 2     // fused ARM kernel: rows per band
+#define CC_FUSED_BAND 2     // fused ARM kernel: rows per band (a multiple of 2)
+#define CC_FUSED_HALO 4     // fused ARM kernel: causal reach in rows (and columns each side)
+// halo planes of the fused ARM's context gradient: the bands above that a
+// band's causal halo rows reach
+#define CC_FUSED_HPLANES ((CC_FUSED_HALO + CC_FUSED_BAND - 1) / CC_FUSED_BAND)
 #ifndef CC_FUSED_MAXWG
 #define CC_FUSED_MAXWG 512  // fused ARM kernel: workgroups per image (each takes every n-th band)
 #endif
+#ifndef CC_UPS_TILE
 #define CC_UPS_TILE 16      // upsampling adjoint: input tile side
+#endif
 #ifndef CC_SYN_BWD_WAVES
 #define CC_SYN_BWD_WAVES 8   // waves per synthesis-backward workgroup (4 or 8)
 #endif

@@ -14,20 +14,21 @@
 // 0/1 permutation matrix, exact in FP32), so no activation passes through
 // LDS, and the weight-gradient products are split BF16 as well.
 //
-// Work: one workgroup (4 wavefronts) per band of 2 rows of one grid, swept in
-// segments of 128 columns; wavefront w owns columns [32 w, 32 w + 32) of the
-// segment in both rows.  The quantised latents of the band and its causal
-// halo (4 rows above, 4 columns each side) are staged in LDS.  The context
+// Work: one workgroup (4 wavefronts) per band of CC_FUSED_BAND rows of one
+// grid, swept in segments of 128 columns; wavefront w owns columns
+// [32 w, 32 w + 32) of the segment in every row of the band.  The quantised
+// latents of the band and its causal halo (4 rows above, 4 columns each
+// side) are staged in LDS.  The context
 // gradient goes to the neighbours without atomics: a wavefront stages its
 // tile's slot gradients in LDS and each lane gathers, for one destination
 // column, the slots that reach it (fixed slot order), adding the sums to the
 // wavefront's private window over the band rows plus that halo; the
 // windows are merged in wavefront order at the end of each segment, so the
-// result is deterministic.  Each band writes its own rows to plane A and
-// the 4 halo rows above it to planes B1 and B2 (for the bands one and two
-// above).  Weight gradients stay in MFMA accumulators across the band and
-// are reduced over the 4 wavefronts in a fixed order into one partial row
-// per band.
+// result is deterministic.  Each band writes its own rows to plane 0 and
+// the 4 halo rows above it to plane q for the rows of the band q above (two
+// planes with 2-row bands, one with 4-row bands).  Weight gradients stay in
+// MFMA accumulators across the band and are reduced over the 4 wavefronts
+// in a fixed order into one partial row per band.
 #include "cc_internal.h"
 
 #include <math.h>
@@ -39,7 +40,8 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr float INV_LN2 = 1.4426950408889634f;
 constexpr int TH = CC_FUSED_BAND;  // band height (rows)
-constexpr int HALO = 4;            // causal reach: rows above, columns each side
+constexpr int HALO = CC_FUSED_HALO;   // causal reach: rows above, columns each side
+constexpr int RP = TH / 2;            // row pairs of a band (IFCE inputs and pooling)
 constexpr int NW = 4;              // wavefronts per workgroup
 constexpr int SW = 32 * NW;        // segment width
 constexpr int WR = SW + 2 * HALO;  // LDS row: segment plus the halo columns
@@ -154,6 +156,7 @@ template <int S, int F, int H1, int H2>
 __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   constexpr int CTX = S + F;
   static_assert(CTX + 1 <= 32 && H1 + 2 <= 32 && H2 + 1 <= 32 && CC_MAX_NIN + 1 <= 32, "shape");
+  static_assert(TH % 2 == 0 && HALO >= TH, "row pairs; every halo row in a band above");
   // The linear stabilizer rides in the first layer's spare output rows H1,
   // H1 + 1 (and its backward in the same columns of the transposed layer):
   // register IS of half HS holds row H1, register IS + 1 row H1 + 1.
@@ -174,8 +177,8 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
   __shared__ float wsum_raw[3 * 32 * 33];
   float(*wsum)[32][33] = reinterpret_cast<float(*)[32][33]>(wsum_raw);
   static_assert(H1 * CTX + H2 * H1 <= 3 * 32 * 33, "weight staging");
-  __shared__ float pwin[CC_MAX_NIN][SW / 2 + 1];   // IFCE inputs of the segment
-  __shared__ float fwin[8][SW / 2];                 // IFCE features per column pair
+  __shared__ float pwin[RP][CC_MAX_NIN][SW / 2 + 1];   // IFCE inputs of the segment, per row pair
+  __shared__ float fwin[RP][8][SW / 2];                 // IFCE features per 2 x 2 block
   __shared__ float dfs[NW][8][32];                  // top-row pair sums of the IFCE gradients
   __shared__ float vec[8][32];      // b1, b2, W3[0], W3[1], Ws[0], Ws[1] by row
   __shared__ float iw[8][CC_MAX_NIN], ib[8];  // IFCE weights [feature][input] (zero padded), biases
@@ -311,19 +314,21 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
     }
   };
   // IFCE inputs of the segment: every input grid is coarser (shift >= 1)
-  // and y0 is even, so both rows share each input row; prefetched into
-  // registers with the window
-  constexpr int NQ = (CC_MAX_NIN * (SW / 2 + 1) + NW * 64 - 1) / (NW * 64);
+  // and y0 is even, so each row pair of the band shares one input row;
+  // prefetched into registers with the window
+  constexpr int NPW = CC_MAX_NIN * (SW / 2 + 1);
+  constexpr int NQ = (RP * NPW + NW * 64 - 1) / (NW * 64);
   float pv[NQ];
   auto load_inputs = [&](int xs, int t0) {
 #pragma unroll
     for (int u = 0; u < NQ; ++u) {
       const int i = t0 + NW * 64 * u;
-      const int q = i / (SW / 2 + 1), c = i - q * (SW / 2 + 1);
+      const int rp = i / NPW, iq = i - rp * NPW;
+      const int q = iq / (SW / 2 + 1), c = iq - q * (SW / 2 + 1);
       float v = 0.0f;
-      if (q < nin) {
+      if (rp < RP && q < nin) {
         const int j = d->isrc[k][q], sh = d->ish[k][q];
-        const int py = y0 >> sh, px = (xs >> sh) + c;
+        const int py = (y0 + 2 * rp) >> sh, px = (xs >> sh) + c;
         if (py < d->gh[j] && px < d->gw[j]) v = d->yhat[d->goff[j] + py * d->gw[j] + px];
       }
       pv[u] = v;
@@ -344,20 +349,21 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
 #pragma unroll
       for (int u = 0; u < NQ; ++u) {
         const int i = tq + NW * 64 * u;
-        if (i < CC_MAX_NIN * (SW / 2 + 1)) (&pwin[0][0])[i] = pv[u];
+        if (i < RP * NPW) (&pwin[0][0][0])[i] = pv[u];
       }
       __syncthreads();
-      // IFCE features, once per column pair (the inputs are constant over
-      // each 2 x 2 block of the band): f = b + W r, inputs in order
-      for (int i = tq; i < F * (SW / 2); i += NW * 64) {
-        const int f = i / (SW / 2), c2 = i - f * (SW / 2);
+      // IFCE features, once per 2 x 2 block (the inputs are constant over
+      // each): f = b + W r, inputs in order
+      for (int i = tq; i < RP * F * (SW / 2); i += NW * 64) {
+        const int rp = i / (F * (SW / 2)), fi = i - rp * (F * (SW / 2));
+        const int f = fi / (SW / 2), c2 = fi - f * (SW / 2);
         const int xp = x0 + 2 * c2;
         float a = ib[f];
         for (int q = 0; q < nin; ++q) {
           const int sh = d->ish[k][q];
-          a += iw[f][q] * pwin[q][(xp >> sh) - (x0 >> sh)];
+          a += iw[f][q] * pwin[rp][q][(xp >> sh) - (x0 >> sh)];
         }
-        fwin[f][c2] = a;
+        fwin[rp][f][c2] = a;
       }
     }
     __syncthreads();
@@ -384,7 +390,7 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
           if (kk < S) {
             v = (&ywin[HALO + r][lc])[hh ? coff(k1) : coff(k0)];
           } else if (kk < CTX && has_ifce) {
-            v = fwin[kk - S][(32 * wave + n) >> 1];
+            v = fwin[r >> 1][kk - S][(32 * wave + n) >> 1];
           }
           cf[s][i] = v;
         }
@@ -494,11 +500,11 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
           const int m = mrow(i, hh);
           if (m >= S && m < CTX) {
             const float pr = dc[i] + __shfl_xor(dc[i], 1);
-            if (r == 0) {
+            if ((r & 1) == 0) {
               dfs[wave][m - S][n] = pr;
             } else if ((n & 1) == 0 && x < w) {
               const int w1 = d->gw[k + 1], n1 = d->gh[k + 1] * w1;
-              d->df[d->dfoff[k][1] + (m - S) * n1 + (y0 >> 1) * w1 + (x >> 1)] = dfs[wave][m - S][n] + pr;
+              d->df[d->dfoff[k][1] + (m - S) * n1 + (y >> 1) * w1 + (x >> 1)] = dfs[wave][m - S][n] + pr;
             }
           }
         }
@@ -558,9 +564,8 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
     // ---- merge the wavefront windows (fixed order) with the carried
     // columns, write the finished columns of this segment and carry the last
     // 2*HALO columns into the next one.  Row rr of the window is grid row
-    // y0 - HALO + rr: rows >= HALO belong to this band (plane A), rows
-    // [HALO - TH, HALO) to the band above (plane B1), rows [0, HALO - TH) to
-    // the band two above (plane B2).
+    // y0 - HALO + rr: rows >= HALO belong to this band (plane 0), the
+    // others to the band q = ceil((HALO - rr) / TH) above (plane q).
     if (bwd > 0) {
       const bool last = seg == nseg - 1;
       for (int i = tq; i < (HALO + TH) * WR; i += NW * 64) {
@@ -580,7 +585,8 @@ __global__ __launch_bounds__(256, 2) void k_arm_fused(Launch Lc, int bwd) {
         }
         const int gy = y0 - HALO + rr, gx = x0 - HALO + c;
         if (gx < 0 || gx >= w || gy < 0 || gy >= h) continue;
-        const int plane = rr >= HALO ? 0 : (rr >= HALO - TH ? 1 : 2);
+        // plane 0: this band's rows; plane q: the rows of the band q above
+        const int plane = rr >= HALO ? 0 : (HALO - rr + TH - 1) / TH;
         d->dc[(size_t)plane * d->n_lat + d->goff[k] + gy * w + gx] = v;
       }
       __syncthreads();

@@ -270,11 +270,12 @@ __device__ __forceinline__ void join_tile(const CDesc* d, int tile, float* rate_
   float g;
   if (d->arm_fused) {
     // planes of the band-tiled kernel: own band, then the halo rows written
-    // by the bands one and two below (the causal reach is 4 rows)
+    // by the bands q = 1 .. CC_FUSED_HPLANES below (the causal reach is 4 rows)
     g = d->dc[i];
     const int band = y / CC_FUSED_BAND, nb = (h + CC_FUSED_BAND - 1) / CC_FUSED_BAND;
-    if (band + 1 < nb) g += d->dc[(size_t)d->n_lat + i];
-    if (band + 2 < nb) g += d->dc[(size_t)2 * d->n_lat + i];
+#pragma unroll
+    for (int q = 1; q <= CC_FUSED_HPLANES; ++q)
+      if (band + q < nb) g += d->dc[(size_t)q * d->n_lat + i];
   } else {
     g = d->dyd[i];
     const float* dc = d->dc + d->goff[k];

@@ -114,6 +114,7 @@ __device__ __forceinline__ float axis_w(const float* h, int o, int i, int n) {
 constexpr int UT = CC_UPS_TILE;   // input tile side
 constexpr int UG = 2 * UT + 6;   // output window side (2*UT + 3 + 3)
 constexpr int UTW = UT + 4;      // input window side (2 each side)
+static_assert(UT * 8 <= 256, "one thread per (tile row, tap) for the axis weights");
 
 __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
   __shared__ float g[UG][UG + 1];
@@ -186,8 +187,8 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
       Bm[q][c] = a;
     }
     __syncthreads();
-    {
-      const int q = tid / UT, p = tid - q * UT;   // 256 = 16 x 16 inputs
+    for (int i = tid; i < UT * UT; i += 256) {
+      const int q = i / UT, p = i - q * UT;
       const int iy = iy0 + q, ix = ix0 + p;
       if (iy < hi && ix < wi) {
         float a = 0.0f;
