@@ -320,7 +320,8 @@ int cc_arm_band_plan(const cc_config* cfg, int H, int W, int nw, int* nbands, in
  * launch stream around every launch of one kernel class ("arm", "syn_bwd",
  * "res_bwd", "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which
  * also applies the latents' Adam update in an encode step and shares its
- * launch with the first pass of the weight-gradient reduction; NULL or "" switches
+ * launch with the first pass of the weight-gradient reduction; "pool", the IFCE
+ * gradient pooling and IFCE weight gradient; NULL or "" switches
  * timing off; the upsampling and residual classes time all levels or layers of
  * one step as one span) by the calls that follow.  cc_timing_read waits for those events and returns the summed
  * duration (ms) and the number of timed launches, then resets the record.

@@ -790,7 +790,7 @@ int quantise(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st)
 
 // Optional live timing of one kernel class with HIP events recorded on the
 // launch stream around each of its launches (see cc_timing_enable).
-enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_RES_BWD = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6 };
+enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_RES_BWD = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6, TK_POOL = 7 };
 struct Timing {
   int kind = TK_NONE;
   int every = 1;                // time one launch in `every`
@@ -972,6 +972,7 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
     const hipStream_t sr = fk.begin();
     RET(arm(s, n, backward ? 1 : 0, sr));
     if (backward && h0.G > 0) {
+      TimeScope ts(TK_POOL, sr);
       RET(cc_launch_pool(plan(s, n, pool_blocks), sr));
     }
   }
@@ -1765,6 +1766,7 @@ int cc_timing_enable(const char* kernel) {
   else if (kernel && !strcmp(kernel, "ups_bwd")) k = TK_UPS_BWD;
   else if (kernel && !strcmp(kernel, "join")) k = TK_JOIN;
   else if (kernel && !strcmp(kernel, "ups_fwd")) k = TK_UPS_FWD;
+  else if (kernel && !strcmp(kernel, "pool")) k = TK_POOL;
   else if (kernel && kernel[0]) return fail(CC_EINVAL, "unknown kernel class '%s'", kernel);
   g_timing.kind = k;
   g_timing.used = 0;
