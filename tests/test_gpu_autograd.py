@@ -77,6 +77,25 @@ def test_modules_match_oracle(mk):
     _close(p.grad.cpu().numpy()[n_arm:], po.grad.numpy()[n_arm:], "ups+syn d/dparams")
 
 
+@pytest.mark.parametrize("mk,H,W", [(wl.config_tiny, 40, 56), (wl.config_tiny, 8, 8),
+                                    (wl.config_tiny, 24, 72), (wl.config_hop, 64, 1088),
+                                    (lambda: wl.ModelConfig(L=8), 128, 384)])
+def test_upsampling_forward_every_tile_shape(mk, H, W):
+    """zhat of the upsampling forward (per-level launches over the fine
+    levels, one workgroup per source grid for the coarse ones) against the
+    oracle: images smaller than a 16 x 16 adjoint tile and ragged against it
+    (L = 4), a wide strip (L = 7), and eight grids (L = 8)."""
+    from paper_2605_02726_amd.autograd import Modules, upsample
+    mc, H, W, yhat, par = _case(mk, H, W, seed=43)
+    cfg = mc.as_dict()
+    mods = Modules(mc, H, W)
+    with torch.no_grad():
+        z = upsample(torch.tensor(yhat, device="cuda"), torch.tensor(par, device="cuda"), mods)
+    P = R.unpack_params(cfg, torch.tensor(par.astype(np.float64)))
+    zo = R.upsample(cfg, P, R.split_latents(cfg, H, W, torch.tensor(yhat.astype(np.float64))))
+    _close(z.cpu().numpy(), zo.numpy(), "zhat")
+
+
 def test_module_gradients_match_finite_differences():
     """Central differences of the wrappers' own forward (FP32, evaluated in
     double from the GPU outputs) against their backward, on random
