@@ -105,11 +105,14 @@ def search(start: dict, knobs, measure, min_gain: float = 0.01):
 
 
 def tune(mc, H: int, W: int, precision: str = "bf16", steps: int = 8, seed: int = 0,
-         cache: Optional[ShapeCache] = None, min_gain: float = 0.01) -> dict:
+         cache: Optional[ShapeCache] = None, min_gain: float = 0.01, repeats: int = 3) -> dict:
     """Fastest launch shape found for this decoder, precision and image size;
     returns {"shape": {...}, "ms_per_step": ..., "default_ms_per_step": ...,
     "trials": [...]} and records it in ``cache``.  A candidate replaces the
-    current best only when it is faster by more than ``min_gain``."""
+    current best only when it is faster by more than ``min_gain``; each
+    candidate's time is the smallest of ``repeats`` runs of ``steps`` steps
+    (a single short run is noisy enough to reorder candidates a few percent
+    apart)."""
     enc = Encoder(mc, torch.from_numpy(wl.synth_image(H, W, seed)), 1e-3, seed,
                   np.zeros(wl.n_latents(mc, H, W), np.float32), wl.init_params(mc, seed),
                   precision=precision)
@@ -125,8 +128,10 @@ def tune(mc, H: int, W: int, precision: str = "bf16", steps: int = 8, seed: int 
 
     def measure(shape):
         enc.set_launch_shape(**shape)
-        ms = _time_steps(enc, clock["t"], steps)
-        clock["t"] += steps + 2
+        ms = float("inf")
+        for _ in range(repeats):
+            ms = min(ms, _time_steps(enc, clock["t"], steps))
+            clock["t"] += steps + 2
         return ms
 
     best, best_ms, default_ms, trials = search(info, knobs, measure, min_gain)

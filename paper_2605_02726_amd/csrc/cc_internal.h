@@ -130,6 +130,20 @@ __device__ __forceinline__ int cc_find_img(const Launch& L, int b) {
   return i;
 }
 
+// Workgroup index within image im, renumbered for the XCDs: the dispatcher
+// hands consecutive workgroups of a launch to the CC_NXCD XCDs in turn, each
+// XCD with its own L2, so here the workgroups of one XCD take consecutive
+// indices and tiles that share halo rows or cache lines mostly run under one
+// L2.  A bijection of [0, nwg): each index does the same work as before, only
+// the XCD it runs on changes, so results do not depend on it.
+#define CC_NXCD 8
+__device__ __forceinline__ int cc_xcd_index(const Launch& L, int im) {
+  const int nwg = L.tile0[im + 1] - L.tile0[im];
+  const int loc = (int)blockIdx.x - L.tile0[im];
+  const int q = nwg / CC_NXCD, r = nwg % CC_NXCD, o = loc % CC_NXCD;
+  return o * q + min(o, r) + loc / CC_NXCD;
+}
+
 // -------------------------------------------------------------- host side
 // Launchers implemented in the kernel translation units.
 struct HostImg;  // defined in cc_api.hip

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_ups_fwd(Launch L, int j) {
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
   const int ho = d->gh[j - 1], wo = d->gw[j - 1], hi = d->gh[j], wi = d->gw[j];
-  const int p = (blockIdx.x - L.tile0[im]) * CC_PIX_TILE + threadIdx.x;
+  const int p = cc_xcd_index(L, im) * CC_PIX_TILE + threadIdx.x;
   if (p >= ho * wo) return;
   const int oy = p / wo, ox = p - oy * wo;
   const CF* hc = (const CF*)(d->theta + d->n_lat + d->p_ups[j]);
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_ups_bwd(Launch L, int j) {
   __shared__ float sh[4][4];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
-  const int wgi = blockIdx.x - L.tile0[im];
+  const int wgi = cc_xcd_index(L, im);
   const int ho = d->gh[j - 1], wo = d->gw[j - 1], hi = d->gh[j], wi = d->gw[j];
   const int ntx = (wi + UT - 1) / UT, ntile = ntx * ((hi + UT - 1) / UT);
   const int ch = wgi / ntile, tile = wgi - ch * ntile;   // one channel of one tile
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_upc_fwd(Launch L, int j) {
   const CDesc* d = (const CDesc*)L.d[im];
   const int hi = d->gh[j], wi = d->gw[j];
   int ch, y0, x0;
-  upc_tile(d, j, blockIdx.x - L.tile0[im], ch, y0, x0);
+  upc_tile(d, j, cc_xcd_index(L, im), ch, y0, x0);
   float k[7];
   conv_kernel7(d, j, k);
   load_window(tchan(d, j, ch), y0, x0, hi, wi, false, win);
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256) void k_upc_bwd(Launch L, int j) {
   __shared__ float sh[4][4];
   const int im = cc_find_img(L, blockIdx.x);
   const CDesc* d = (const CDesc*)L.d[im];
-  const int wgi = blockIdx.x - L.tile0[im];
+  const int wgi = cc_xcd_index(L, im);
   const int hi = d->gh[j], wi = d->gw[j], n = hi * wi;
   const int tid = threadIdx.x;
   int ch, y0, x0;
@@ -1220,7 +1220,7 @@ __global__ __launch_bounds__(CC_PIX_TILE) void k_res_fwd(Launch Lc, int r, int l
   __shared__ double sh[CC_PIX_TILE / 64];
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
-  const int wgi = blockIdx.x - Lc.tile0[im];
+  const int wgi = cc_xcd_index(Lc, im);
   const int H = d->H, W = d->W, n = H * W;
   const int p = wgi * CC_PIX_TILE + threadIdx.x;
   const bool valid = p < n;
@@ -1352,7 +1352,7 @@ __global__ __launch_bounds__(512, 4) void k_res_bwd(Launch Lc, int r, int src_b)
   __shared__ float wsum[8][RG];
   const int im = cc_find_img(Lc, blockIdx.x);
   const CDesc* d = (const CDesc*)Lc.d[im];
-  const int wgi = blockIdx.x - Lc.tile0[im];
+  const int wgi = cc_xcd_index(Lc, im);
   const int nwg = d->res_nwg;
   const int H = d->H, W = d->W, n = H * W;
   const int tid = threadIdx.x, lane = tid & 63;
