@@ -204,7 +204,9 @@ int cc_launch_nnq(const Launch& l, const NnqPack& a, hipStream_t st);
 #define CC_UPC_TW 64        // and columns
 #define CC_UPS_COARSE 2048  // upsampling levels whose output grid has at most this many positions
                             // run as one workgroup per source grid, all such levels in LDS
+#ifndef CC_UPS_CHAIN_T
 #define CC_UPS_CHAIN_T 1024 // threads of those workgroups
+#endif
 #define CC_SOAP_TAB 12       // SOAP table row: poff, numel, ndim, dims[4], factor offsets[4], pad
 #define CC_SOAP_MAXDIM 48    // SOAP: dimensions above this get no Kronecker factor
 #define CC_SOAP_MAXNUMEL 1024  // SOAP: largest parameter tensor
