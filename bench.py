@@ -457,7 +457,7 @@ def main():
         cases = [(p, False) for p in plist] + ([] if args.no_soap else [(plist[-1], True)])
         for p, hyp in cases:
             mc_t = wl.config_hop_hyper() if hyp else wl.config_hop()
-            r = autotune.tune(mc_t, 512, 768, p, steps=60, min_gain=0.015)
+            r = autotune.tune(mc_t, 512, 768, p, steps=60, min_gain=0.005, rounds=3)
             key = p + ("_hyper" if hyp else "")
             shapes[key] = r["shape"]
             tuning[key] = {"shape": r["shape"], "trials": len(r["trials"]),

@@ -58,3 +58,22 @@ def test_search_is_coordinate_descent_with_a_minimum_gain():
     # a gain below min_gain keeps the earlier shape
     best, _, _, _ = at.search({"a": 1, "b": 10}, [("b", (20,))], measure, min_gain=0.01)
     assert best == {"a": 1, "b": 10}
+
+
+def test_search_rounds_revisit_knobs_that_interact():
+    """With a knob whose best value depends on another, a second sweep from
+    the first sweep's best finds the joint optimum; shapes timed once are not
+    timed again, and a round that changes nothing ends the search."""
+    cost = {(1, 10): 1.0, (2, 10): 0.995, (1, 20): 0.99, (2, 20): 0.80, (3, 10): 1.2, (3, 20): 1.2}
+    calls = []
+
+    def measure(shape):
+        calls.append((shape["a"], shape["b"]))
+        return cost[(shape["a"], shape["b"])]
+    knobs = [("a", (1, 2, 3)), ("b", (10, 20))]
+    best, ms, _, _ = at.search({"a": 1, "b": 10}, knobs, measure, min_gain=0.01, rounds=1)
+    assert best == {"a": 1, "b": 10}          # (2, 10) and (1, 20) each gain < 1%
+    calls.clear()
+    best, ms, _, trials = at.search({"a": 1, "b": 10}, knobs, measure, min_gain=0.005, rounds=3)
+    assert best == {"a": 2, "b": 20} and ms == 0.80
+    assert len(calls) == len(set(calls)) == len(trials)
