@@ -321,7 +321,8 @@ int cc_arm_band_plan(const cc_config* cfg, int H, int W, int nw, int* nbands, in
  * "res_bwd", "ups_fwd", "ups_bwd", "join" -- the latent-gradient join, which
  * also applies the latents' Adam update in an encode step and shares its
  * launch with the first pass of the weight-gradient reduction; "pool", the IFCE
- * gradient pooling and IFCE weight gradient; NULL or "" switches
+ * gradient pooling and IFCE weight gradient; "syn_fwd", the synthesis trunk,
+ * residual layers and MSE forward; NULL or "" switches
  * timing off; the upsampling and residual classes time all levels or layers of
  * one step as one span) by the calls that follow.  cc_timing_read waits for those events and returns the summed
  * duration (ms) and the number of timed launches, then resets the record.

@@ -790,7 +790,7 @@ int quantise(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st)
 
 // Optional live timing of one kernel class with HIP events recorded on the
 // launch stream around each of its launches (see cc_timing_enable).
-enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_RES_BWD = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6, TK_POOL = 7 };
+enum { TK_NONE = 0, TK_ARM = 1, TK_SYN_BWD = 2, TK_RES_BWD = 3, TK_UPS_BWD = 4, TK_JOIN = 5, TK_UPS_FWD = 6, TK_POOL = 7, TK_DIST_FWD = 8 };
 struct Timing {
   int kind = TK_NONE;
   int every = 1;                // time one launch in `every`
@@ -980,7 +980,10 @@ int run_step(cc_state* const* s, int n, const cc_step_params* p, hipStream_t st,
     TimeScope ts(TK_UPS_FWD, st);
     RET(ups_forward(s, n, st));
   }
-  RET(forward_syn(s, n, 1, st));
+  {
+    TimeScope ts(TK_DIST_FWD, st);
+    RET(forward_syn(s, n, 1, st));
+  }
   if (backward) {
     const Launch lp = plan(s, n, [](const DevDesc& h) { return h.res_nwg; });
     int src_b = 0;
@@ -1767,6 +1770,7 @@ int cc_timing_enable(const char* kernel) {
   else if (kernel && !strcmp(kernel, "join")) k = TK_JOIN;
   else if (kernel && !strcmp(kernel, "ups_fwd")) k = TK_UPS_FWD;
   else if (kernel && !strcmp(kernel, "pool")) k = TK_POOL;
+  else if (kernel && !strcmp(kernel, "syn_fwd")) k = TK_DIST_FWD;
   else if (kernel && kernel[0]) return fail(CC_EINVAL, "unknown kernel class '%s'", kernel);
   g_timing.kind = k;
   g_timing.used = 0;
